@@ -1,0 +1,126 @@
+// ||X||^2 = nu' [V'V]^d nu (Lemma 3.4 applied to X; Section 3.3).
+//
+// The p x p Gram matrix V'V is visited in 128 x 128 tiles on fp64 matrix
+// cores and never stored.  By symmetry only tiles on or above the diagonal
+// are formed; an off-diagonal tile stands for itself and its mirror and is
+// counted twice.  Each block writes one fp64 partial; a single-block kernel
+// sums the partials in a fixed order, so the result is bitwise repeatable.
+#include "kcommon.hpp"
+#include "kernels.hpp"
+
+namespace symtd {
+
+// (row tile, column tile) of upper-triangular tile pair number b, enumerated
+// row by row: row t holds the pairs (t, t), (t, t+1), ..., (t, T-1).
+__device__ __forceinline__ void tri_pair(int64_t b, int64_t T, int64_t& tr, int64_t& tc) {
+  const double bb = (double)(2 * T + 1);
+  int64_t t = (int64_t)((bb - sqrt(bb * bb - 8.0 * (double)b)) * 0.5);
+  if (t < 0) t = 0;
+  if (t > T - 1) t = T - 1;
+  auto start = [T](int64_t s) { return s * T - (s * (s - 1)) / 2; };
+  while (t > 0 && start(t) > b) --t;
+  while (t + 1 < T && start(t + 1) <= b) ++t;
+  tr = t;
+  tc = t + (b - start(t));
+}
+
+template <typename S, bool VEC>
+__global__ __launch_bounds__(256) void k_normx(NormXArgs<S> a) {
+  using acc_t = v4d;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  int64_t tr, tc;
+  tri_pair(blockIdx.x, a.ntile, tr, tc);
+  const int64_t rbase = tr * 128 + (wave >> 1) * 64;
+  const int64_t cbase = tc * 128 + (wave & 1) * 64;
+
+  const S* rp[4]; bool rok[4];
+  const S* cp[4]; bool cok[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int64_t lr = rbase + 16 * m + c, lc = cbase + 16 * m + c;
+    rok[m] = lr < a.p; cok[m] = lc < a.p;
+    rp[m] = a.V + (rok[m] ? lr : 0) * a.ldv;
+    cp[m] = a.V + (cok[m] ? lc : 0) * a.ldv;
+  }
+  acc_t acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[m][q] = acc_t{0, 0, 0, 0};
+
+  const int64_t n = a.n;
+  Quad<S> rq[4], cq[4];
+  for (int64_t i0 = 0; i0 < n; i0 += 16) {
+    const int64_t i = i0 + 4 * g;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      load4<S, VEC>(rq[m], rp[m], i, n, rok[m]);
+      load4<S, VEC>(cq[m], cp[m], i, n, cok[m]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc[m][q] = Mfma<double>::mac((double)rq[m].e[s], (double)cq[q].e[s], acc[m][q]);
+  }
+
+  // acc[m][q][v] = (V'V)[rbase + 16m + row(g, v)][cbase + 16q + c]
+  double nc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t l = cbase + 16 * q + c;
+    nc[q] = l < a.p ? a.nu[l] : 0.0;
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t l = rbase + 16 * m + Mfma<double>::row(g, v);
+      const double nr = l < a.p ? a.nu[l] : 0.0;
+      double rs = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rs += nc[q] * ipow(acc[m][q][v], a.d);
+      sum += nr * rs;
+    }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) sum += __shfl_xor(sum, o);
+  __shared__ double red[4];
+  if (lane == 0) red[wave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double w = (tr == tc) ? 1.0 : 2.0;
+    a.part[blockIdx.x] = w * (((red[0] + red[1]) + red[2]) + red[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < a.count; e += 256) acc += a.part[e];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.out[0] = s[0];
+}
+
+void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<float>& a) {
+  if (vec) hipLaunchKernelGGL((k_normx<float, true>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_normx<float, false>), grid, dim3(256), 0, st, a);
+}
+void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<double>& a) {
+  if (vec) hipLaunchKernelGGL((k_normx<double, true>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_normx<double, false>), grid, dim3(256), 0, st, a);
+}
+void launch_reduce(hipStream_t st, const ReduceArgs& a) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, a);
+}
+
+}  // namespace symtd

@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serial", action="store_true", help="model terms on the caller's stream")
+    ap.add_argument("--g1-blocks", type=int, default=0)
+    ap.add_argument("--g2-splits", type=int, default=0)
     return ap.parse_args()
 
 
@@ -97,6 +100,9 @@ def main():
     nud = torch.from_numpy(nu).to(dev)
     lamd = torch.from_numpy(lam).to(dev)
     ctx = S.Context(0)
+    S.symtd_set_tuning(ctx, S.TUNE_SERIAL, int(args.serial))
+    S.symtd_set_tuning(ctx, S.TUNE_G1_BLOCKS, args.g1_blocks)
+    S.symtd_set_tuning(ctx, S.TUNE_G2_SPLITS, args.g2_splits)
     out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(r, dtype=torch.float64, device=dev),
            S.colmajor(torch.empty(n, r, dtype=dt, device=dev)))
     stream = torch.cuda.current_stream()
@@ -118,7 +124,7 @@ def main():
     for k, name in enumerate(S.profile_names()):
         ms, cnt = S.symtd_profile_read(ctx, k)
         if cnt:
-            per_kernel[name] = {"avg_us": 1e3 * ms / cnt, "launches": cnt}
+            per_kernel[name] = {"avg_us": 1e3 * ms / cnt, "launches": cnt, "step_us": 1e3 * ms / args.steps}
     S.symtd_profile_reset(ctx)
 
     sec = (t1 - t0) / args.steps
@@ -126,8 +132,11 @@ def main():
     flop_gemm = 2.0 * n * p * r                       # each of the two products
     flop_step = 2 * flop_gemm + 4.0 * n * r * r       # plus B = A'A and A D_lambda C
     peak = PEAK_TFLOPS[args.prec]
-    dom = max(("gemm1", "gemm2"), key=lambda k: per_kernel.get(k, {"avg_us": 0})["avg_us"])
-    dom_us = per_kernel[dom]["avg_us"]
+    # the dominant product; with r > 16 * (subtiles per launch) it runs as
+    # several column-group launches, so its algorithmic flops per step are
+    # divided by its summed launch time per step
+    dom = max(("gemm1", "gemm2"), key=lambda k: per_kernel.get(k, {"step_us": 0})["step_us"])
+    dom_us = per_kernel[dom]["step_us"]
     achieved = flop_gemm / (dom_us * 1e-6) / 1e12
     traffic = TRAFFIC_BYTES.get((args.prec, dom))
 
@@ -148,8 +157,9 @@ def main():
                    "d": d, "n": n, "r": r, "p": p, "precision": args.prec, "storage": args.prec},
         "step_mfma_frac": flop_step * evals / (peak * 1e12),
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic},
-        "kernels_us": {k: round(v["avg_us"], 2) for k, v in per_kernel.items()},
+                     "frac": achieved / peak, "traffic": traffic,
+                     "launches_per_step": per_kernel[dom]["launches"] / args.steps},
+        "kernels_us_per_step": {k: round(v["step_us"], 2) for k, v in per_kernel.items()},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(Vs, nu, As, lam, d, args.cpu_seconds)

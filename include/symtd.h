@@ -109,6 +109,24 @@ symtd_status symtd_normX(symtd_ctx* ctx, void* stream, symtd_dtype dt,
                          int d, double* alpha);
 
 /*
+ * Work-split tuning of the evaluation kernels (used by the autotuner and by
+ * tests that force particular splits). Keys:
+ *   SYMTD_TUNE_G1_BLOCKS  blocks sharing the first product V'A (0 = automatic:
+ *                         one per compute unit, never more than the number of
+ *                         observation slabs; larger requests are clamped)
+ *   SYMTD_TUNE_G2_SPLITS  splits of the observations in the second product V W
+ *                         (0 = automatic: about one block per compute unit)
+ *   SYMTD_TUNE_SERIAL     1 = run the small model-term kernels (A'A, A D C) on
+ *                         the caller's stream before the products; 0 (default)
+ *                         = on the context's side stream, overlapped with them
+ * Values must be >= 0; results do not depend on them beyond rounding order.
+ */
+typedef enum symtd_tune_key {
+  SYMTD_TUNE_G1_BLOCKS = 0, SYMTD_TUNE_G2_SPLITS = 1, SYMTD_TUNE_SERIAL = 2
+} symtd_tune_key;
+symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value);
+
+/*
  * Per-kernel timing. While enabled, every kernel the context launches is
  * bracketed by HIP events on the launch stream; symtd_profile_read
  * synchronises those events and returns, for kernel `which`, the summed

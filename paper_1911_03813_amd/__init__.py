@@ -48,6 +48,7 @@ SIGNATURES = {
     "symtd_fg": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int,
                         _dbl, _int, _vp, _vp, _vp, _i64]),
     "symtd_normX": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _vp]),
+    "symtd_set_tuning": (_int, [_vp, _int, _i64]),
     "symtd_profile_enable": (_int, [_vp, _int]),
     "symtd_profile_reset": (_int, [_vp]),
     "symtd_profile_read": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
@@ -192,6 +193,14 @@ def symtd_normX(ctx: Context, V, nu, d: int, out=None, stream=None):
     st = lib().symtd_normX(ctx.handle, _stream(stream), _dt(V), Vp, ldv, nup, n, p, int(d), _vec(a, "alpha", 1))
     _check(ctx, st)
     return a
+
+
+TUNE_G1_BLOCKS, TUNE_G2_SPLITS, TUNE_SERIAL = 0, 1, 2
+
+
+def symtd_set_tuning(ctx: Context, key: int, value: int):
+    """Override a work-split choice of the evaluation kernels (0 = automatic)."""
+    _check(ctx, lib().symtd_set_tuning(ctx.handle, int(key), int(value)))
 
 
 def symtd_profile_enable(ctx: Context, enable: bool = True):

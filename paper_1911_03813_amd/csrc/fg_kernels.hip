@@ -1,23 +1,29 @@
 // Kernels of the objective/gradient evaluation (Algorithm 2, fg_implicit).
 //
-//   gemm1   Z = V'A on matrix cores, one 16-row slab of observations per
-//           M subtile.  Epilogue: W = D_nu Z^{d-1} (eq. (Y) before the outer
-//           product), written in a packed layout that the second product
-//           reads with one coalesced vector load per lane, and fp64 partial
-//           column sums of nu_l z_lj^d (= w_j by Lemmas 3.2 and 3.5).
-//   gemm2   Y = V W on matrix cores, split over the observations (split-K);
-//           each split writes its own partial Y, so no atomics are used.
-//   gram    B = A'A and C = B^{d-1} in fp64.
-//   final_G   Y = fixed-order fp64 sum of the partials; G_A = -2d (Y - A D_lambda C) D_lambda.
-//   final_s   w = fixed-order fp64 sum of the column partials; u = (B*C) lambda;
-//             f = alpha + lambda'u - 2 w'lambda; g_lambda = -2 (w - u).
+//   gemm1     Z = V'A on matrix cores, 16 observations (one slab) at a time.
+//             Epilogue: W = D_nu Z^{d-1} (eq. (Y) before the outer product),
+//             written in a packed layout that gemm2 reads with one coalesced
+//             vector load per lane, and fp64 column sums of nu_l z_lj^d
+//             (= w_j by Lemmas 3.2 and 3.5), one partial row per wave.
+//   gemm2     Y = V W on matrix cores, split over the observations; each split
+//             writes its own partial Y (no atomics, fixed reduction order).
+//   gram_part / gram_fin   B = A'A in fp64 (split over rows, then summed),
+//             C = B^{d-1}.
+//   ymodel    Y_M = A D_lambda C in fp64 (the model's own TTSVs, M a_j^{d-1}).
+//   final_s / final_f   w = fixed-order sum of the column partials,
+//             u = (B*C) lambda, g_lambda = -2 (w - u),
+//             f = alpha + lambda'u - 2 w'lambda.
+//   final_G   G_A = -2d (Y - Y_M) D_lambda with Y the fixed-order fp64 sum of
+//             the gemm2 partials.
 //
 // Packed W layout: element (l, j) with l = 16*b + row(g, s) and j = 16*t + c
 // lives at ((b * nt_tot + t) * 64 + 16*g + c) * 4 + s, where row(g, s) is the
 // MFMA output row of lane group g, element s (Mfma<T>::row).  That is exactly
 // the order in which gemm1's accumulator registers come out, and exactly the
 // B-operand order gemm2 needs when its k index at step s is
-// l = 16*b + row(g, s).
+// l = 16*b + row(g, s).  Rows l >= p hold zeros (their weight nu is zero).
+#include <type_traits>
+
 #include "kcommon.hpp"
 #include "kernels.hpp"
 
@@ -25,138 +31,383 @@ namespace symtd {
 
 // ---------------------------------------------------------------------------
 // gemm1 + epilogue
+//
+// A block of G1_WAVES waves works in lockstep on one slab of
+// 16*G1_MT*G1_WAVES observations (16*G1_MT per wave).  The k range (the n covariates) is cut into
+// chunks of KCH = 4*QPC; for every chunk the block moves the slab's
+// observation columns and the factor columns into LDS, each column as one
+// contiguous run of 128 bytes (QPC quads of 4 elements), and the waves read
+// their MFMA fragments from LDS.  LDS holds a column's quads at a swizzled
+// slot (quad q of column col at col*QPC + (q ^ ((col/2) mod QPC))), so the 16
+// columns of one fragment read fall in distinct banks.
+//
+// When the observations are 16-byte aligned with n a multiple of 4, the
+// chunk's 16-byte pieces go from global memory straight into LDS
+// (global_load_lds): every lane fetches the piece whose LDS slot is its own,
+// and every thread issues the same number of pieces per chunk, so a wave can
+// wait for exactly one chunk with vmcnt.  Chunks rotate through G1_STAGES
+// LDS stages, G1_STAGES-1 of them in flight while one is multiplied.  Other
+// layouts pass through registers with two stages.  The factors are read from
+// a zero-padded copy (Apad) so that they never need masking.
+//
+// The (slab, chunk) pairs are numbered slab-major and every block takes one
+// contiguous range of them (stream-K), so all blocks get the same work to
+// within one chunk.  There are never more blocks than slabs, so a slab is
+// shared by at most two blocks: the block holding its first chunks owns it;
+// the block holding its last chunks (at the start of its range) publishes
+// that partial accumulator through `part` and raises its `flag`; the owner,
+// which reaches the slab at the end of its own range, adds the partial,
+// lowers the flag again and runs the epilogue.  A block waits only after its
+// own work, and only for its successor, which publishes before it waits for
+// anything, so the wait always ends even when not every block is resident;
+// a spin limit guards it regardless.
 // ---------------------------------------------------------------------------
-template <typename T, int MT, int NT, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm1(G1Args<T> a) {
-  using acc_t = typename Mfma<T>::acc_t;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int g = lane >> 4, c = lane & 15;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MT);
+template <typename T>
+struct G1Shape {
+  static constexpr int QPC = G1_RUN / (4 * (int)sizeof(T));   // quads per column per chunk
+  static constexpr int KCH = 4 * QPC;                         // k values per chunk
+};
 
-  const T* vp[MT];
-  bool vok[MT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int64_t l = row0 + 16 * m + c;
-    vok[m] = l < a.p;
-    vp[m] = a.V + (vok[m] ? l : 0) * a.ldv;
-  }
-  const T* ap[NT];
-  bool aok[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int j = a.col0 + 16 * t + c;
-    aok[t] = j < a.r;
-    ap[t] = a.A + (int64_t)(aok[t] ? j : 0) * a.lda;
-  }
+// s_waitcnt immediate that waits until at most `n` vector-memory operations
+// of this wave are outstanding (other counters untouched).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <typename T, int NT, bool DMA>
+__global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
+  using acc_t = typename Mfma<T>::acc_t;
+  constexpr int NW = G1_WAVES;
+  constexpr int MT = G1_MT;
+  constexpr int NTH = 64 * NW;
+  constexpr int NS = G1_STAGES;
+  constexpr int QPC = G1Shape<T>::QPC;
+  constexpr int KCH = G1Shape<T>::KCH;
+  constexpr int H = (int)sizeof(T) / 4;          // 16-byte pieces per quad
+  constexpr int VCOLS = 16 * MT * NW;            // observation columns of a block slab
+  constexpr int VQ = VCOLS * QPC;                // quads of a chunk
+  constexpr int AQ = 16 * NT * QPC;
+  constexpr int VP = (VQ * H + NTH - 1) / NTH;   // 16-byte pieces per thread and chunk
+  constexpr int AP = (AQ * H + NTH - 1) / NTH;
+  constexpr int DPC = VP + AP;                   // DMA instructions per thread and chunk
+  constexpr int PART = NW * MT * NT * 4 * 64;    // elements of one block's published partial
+  static_assert(NS == 2 || NS == 3, "the chunk loop below is written for two or three stages");
+  static_assert(QPC >= 4 && (QPC & (QPC - 1)) == 0, "chunk run length");
+  // LDS stages as distinct objects, so that the compiler can tell the loads
+  // filling one stage from the reads of another; each is padded to whole
+  // rounds of pieces so that every thread moves the same number of them
+  __shared__ Quad<T> lv0[VP * NTH / H], lv1[VP * NTH / H], lv2[NS > 2 ? VP * NTH / H : 1];
+  __shared__ Quad<T> la0[AP * NTH / H], la1[AP * NTH / H], la2[NS > 2 ? AP * NTH / H : 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t B = a.nblocks;
+  const int64_t blk = blockIdx.x;
+  const int64_t n = a.n;
+  const int64_t KC = (n + KCH - 1) / KCH;        // chunks per slab (the last may be ragged)
+  const int64_t U = (int64_t)a.nslab * KC;
+  const int64_t u0 = blk * U / B, u1 = (blk + 1) * U / B;
+  const int tg = a.col0 >> 4;
+  const int dm1 = a.d - 1;
 
   acc_t acc[MT][NT];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
-
-  Quad<T> va0[MT], aa0[NT], va1[MT], aa1[NT];
-  const int64_t n = a.n;
-  const int64_t nfull = n & ~(int64_t)15;
-
-  auto load = [&](Quad<T>(&va)[MT], Quad<T>(&aa)[NT], int64_t i0) {
-    const int64_t i = i0 + 4 * g;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) load4<T, VEC>(va[m], vp[m], i, n, vok[m]);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) load4<T, VEC>(aa[t], ap[t], i, n, aok[t]);
-  };
-  auto mma = [&](const Quad<T>(&va)[MT], const Quad<T>(&aa)[NT]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(va[m].e[s], aa[t].e[s], acc[m][t]);
-  };
-
-  if (nfull > 0) {
-    load(va0, aa0, 0);
-    for (int64_t i0 = 0;; i0 += 32) {
-      if (i0 + 16 < nfull) load(va1, aa1, i0 + 16);
-      mma(va0, aa0);
-      if (i0 + 16 >= nfull) break;
-      if (i0 + 32 < nfull) load(va0, aa0, i0 + 32);
-      mma(va1, aa1);
-      if (i0 + 32 >= nfull) break;
-    }
-  }
-  if (nfull < n) {  // ragged tail of the k range
-    load(va0, aa0, nfull);
-    mma(va0, aa0);
-  }
-
-  // Epilogue.  acc[m][t][v] = z at row l = row0 + 16m + row(g, v), column
-  // j = col0 + 16t + c.
-  const int dm1 = a.d - 1;
   double wsum[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) wsum[t] = 0.0;
-  const int64_t nblk = ((int64_t)a.p + 15) >> 4;
+
+  auto swz = [](int col, int q) { return col * QPC + (q ^ ((col >> 1) & (QPC - 1))); };
+  auto unswz = [](int P, int& col, int& q) { col = P / QPC; q = (P % QPC) ^ ((col >> 1) & (QPC - 1)); };
+  auto vcolumn = [&](int64_t sl, int col) {
+    int64_t l = (int64_t)VCOLS * sl + col;
+    return a.V + (l < a.p ? l : (int64_t)a.p - 1) * a.ldv;    // columns past p: weight 0
+  };
+
+  // DMA of chunk kc of slab sl into one stage (same instruction count on every thread)
+  auto dma = [&](Quad<T>* lv, Quad<T>* la, int64_t sl, int64_t kc) {
+    const int64_t k0 = kc * KCH;
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    Quad<T> wq[NT];
+    for (int i = 0; i < VP; ++i) {
+      const int P16 = tid + NTH * i;
+      const T* src = a.V;                         // padding pieces: any valid address
+      if (P16 < VQ * H) {
+        int col, q;
+        unswz(P16 / H, col, q);
+        int64_t k = k0 + 4 * q;
+        k = k + 3 < n ? k : n - 4;                // whole quads past n: any valid quad
+        src = vcolumn(sl, col) + k + (P16 % H) * (4 / H);
+      }
+      __builtin_amdgcn_global_load_lds((const void*)src,
+          (__attribute__((address_space(3))) void*)((char*)lv + 16 * (NTH * i + 64 * wave)), 16, 0, 0);
+    }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t l = row0 + 16 * m + Mfma<T>::row(g, v);
-      const double nl = (l < a.p) ? a.nu[l] : 0.0;
+    for (int i = 0; i < AP; ++i) {
+      const int P16 = tid + NTH * i;
+      const T* src = a.Apad;
+      if (P16 < AQ * H) {
+        int col, q;
+        unswz(P16 / H, col, q);
+        src = a.Apad + (int64_t)(a.col0 + col) * a.ldap + k0 + 4 * q + (P16 % H) * (4 / H);
+      }
+      __builtin_amdgcn_global_load_lds((const void*)src,
+          (__attribute__((address_space(3))) void*)((char*)la + 16 * (NTH * i + 64 * wave)), 16, 0, 0);
+    }
+  };
+
+  // register path (any alignment): global -> registers -> LDS, two stages
+  constexpr int VQT = (VQ + NTH - 1) / NTH, AQT = (AQ + NTH - 1) / NTH;
+  Quad<T> rv[DMA ? 1 : VQT], ra[DMA ? 1 : AQT];
+  auto gload = [&](int64_t sl, int64_t kc) {
+    const int64_t k0 = kc * KCH;
+    const bool rag = k0 + KCH > n;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const double z = (double)acc[m][t][v];
-        const double zp = ipow(z, dm1);
-        const double wv = nl * zp;
-        wsum[t] += wv * z;
-        wq[t].e[v] = (T)wv;
+    for (int i = 0; i < (DMA ? 0 : VQT); ++i) {
+      const int P = tid + NTH * i;
+      if (P < VQ) {
+        const int col = P / QPC, q = P % QPC;
+        const T* src = vcolumn(sl, col);
+        const int64_t k = k0 + 4 * q;
+        if (!rag) { rv[i].e[0] = src[k]; rv[i].e[1] = src[k + 1]; rv[i].e[2] = src[k + 2]; rv[i].e[3] = src[k + 3]; }
+        else load_tail(rv[i], src, k, n);
       }
     }
-    const int64_t b = (row0 >> 4) + m;
-    if (b < nblk) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        vstore4(a.Wp + (((b * a.nt_tot + (a.col0 >> 4) + t) * 64) + lane) * 4, wq[t]);
+    for (int i = 0; i < (DMA ? 0 : AQT); ++i) {
+      const int P = tid + NTH * i;
+      if (P < AQ) {
+        const int col = P / QPC, q = P % QPC;
+        vload4(ra[i], a.Apad + (int64_t)(a.col0 + col) * a.ldap + k0 + 4 * q);
+      }
+    }
+  };
+  auto lstore = [&](Quad<T>* lv, Quad<T>* la) {
+#pragma unroll
+    for (int i = 0; i < (DMA ? 0 : VQT); ++i) {
+      const int P = tid + NTH * i;
+      if (P < VQ) lv[swz(P / QPC, P % QPC)] = rv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < (DMA ? 0 : AQT); ++i) {
+      const int P = tid + NTH * i;
+      if (P < AQ) la[swz(P / QPC, P % QPC)] = ra[i];
+    }
+  };
+
+  // multiply one chunk held in an LDS stage; the fragments of 16-k group jg+1
+  // are read from LDS while group jg is multiplied
+  auto compute = [&](const Quad<T>* lv, const Quad<T>* la) {
+    constexpr int J = QPC / 4;
+    Quad<T> fv[2][MT], fa[2][NT];
+    auto frag = [&](int b, int jg) {
+      const int q = 4 * jg + g;            // this lane's quad: k = k0 + 16 jg + 4 g + s
+#pragma unroll
+      for (int m = 0; m < MT; ++m) fv[b][m] = lv[swz(16 * (MT * wave + m) + c, q)];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) fa[b][t] = la[swz(16 * t + c, q)];
+    };
+    auto mfma = [&](int b) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(fv[b][m].e[s], fa[b][t].e[s], acc[m][t]);
+    };
+    frag(0, 0);
+#pragma unroll
+    for (int jg = 0; jg < J; ++jg) {
+      if (jg + 1 < J) frag((jg + 1) & 1, jg + 1);
+      mfma(jg & 1);
+    }
+  };
+  // wait until chunk kc (with `later` chunks issued after it) has landed, then
+  // the block-wide barrier: everyone's pieces are in, and the stage read in the
+  // previous step is free again
+  auto arrive = [&](int later) {
+    if (later >= 1) wait_vm<DPC>();
+    else wait_vm<0>();
+    __syncthreads();
+  };
+
+  if (u0 < u1) {
+    int64_t sl = u0 / KC, kb = u0 - sl * KC;
+    const int64_t sl_last = (u1 - 1) / KC;
+    while (true) {
+      const int64_t ke = (sl == sl_last) ? u1 - sl * KC : KC;
+      const int64_t nk = ke - kb;
+      if constexpr (DMA) {
+        if constexpr (NS == 3) {
+          // chunk kb+q lives in stage q mod 3
+          dma(lv0, la0, sl, kb);
+          if (nk > 1) dma(lv1, la1, sl, kb + 1);
+          int64_t q = 0;
+          for (; q + 3 <= nk; q += 3) {
+            arrive((int)min((int64_t)1, nk - 1 - q));
+            if (q + 2 < nk) dma(lv2, la2, sl, kb + q + 2);
+            compute(lv0, la0);
+            arrive((int)min((int64_t)1, nk - 2 - q));
+            if (q + 3 < nk) dma(lv0, la0, sl, kb + q + 3);
+            compute(lv1, la1);
+            arrive((int)min((int64_t)1, nk - 3 - q));
+            if (q + 4 < nk) dma(lv1, la1, sl, kb + q + 4);
+            compute(lv2, la2);
+          }
+          // fewer than three chunks remain, in stages 0, 1
+          if (q < nk) { arrive((int)min((int64_t)1, nk - 1 - q)); compute(lv0, la0); }
+          if (q + 1 < nk) { arrive(0); compute(lv1, la1); }
+        } else {
+          // chunk kb+q lives in stage q mod 2
+          dma(lv0, la0, sl, kb);
+          int64_t q = 0;
+          for (; q + 2 <= nk; q += 2) {
+            arrive(0);
+            dma(lv1, la1, sl, kb + q + 1);
+            compute(lv0, la0);
+            arrive(0);
+            if (q + 2 < nk) dma(lv0, la0, sl, kb + q + 2);
+            compute(lv1, la1);
+          }
+          if (q < nk) { arrive(0); compute(lv0, la0); }
+        }
+      } else {
+        gload(sl, kb);
+        lstore(lv0, la0);
+        __syncthreads();
+        int64_t kc = kb;
+        for (; kc + 1 < ke; kc += 2) {
+          gload(sl, kc + 1);
+          compute(lv0, la0);
+          lstore(lv1, la1);
+          __syncthreads();
+          if (kc + 2 < ke) gload(sl, kc + 2);
+          compute(lv1, la1);
+          if (kc + 2 < ke) lstore(lv0, la0);
+          __syncthreads();
+        }
+        if (kc < ke) compute(lv0, la0);
+      }
+      __syncthreads();   // every stage is read before the next slab overwrites it
+
+      if (kb > 0) {
+        // not the owner: publish this block's partial for the previous block
+        T* pp = a.part + blk * PART + (int64_t)wave * (MT * NT * 4 * 64);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            Quad<T> q4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) q4.e[v] = acc[m][t][v];
+            vstore4(pp + ((m * NT + t) * 64 + lane) * 4, q4);
+          }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // each wave's stores are visible device-wide
+        __syncthreads();                                      // ... before the flag is raised
+        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (ke < KC) {
+          // the next block holds chunks [ke, KC) of this slab
+          int spins = 0;
+          while (__builtin_amdgcn_readfirstlane(
+                     __hip_atomic_load(a.flag + blk + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1 << 24)) {
+              __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+          const T* pp = a.part + (blk + 1) * PART + (int64_t)wave * (MT * NT * 4 * 64);
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              Quad<T> q4;
+              vload4(q4, pp + ((m * NT + t) * 64 + lane) * 4);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[m][t][v] += q4.e[v];
+            }
+          __syncthreads();   // every wave has read the partial before the flag is lowered
+          if (tid == 0) __hip_atomic_store(a.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // epilogue: acc[m][t][v] = z at l = 16 b + row(g, v), j = col0 + 16t + c
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const int64_t b = (int64_t)NW * MT * sl + MT * wave + m;   // 16-observation block
+          double nl[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t l = 16 * b + Mfma<T>::row(g, v);
+            nl[v] = (l < a.p) ? a.nu[l] : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            Quad<T> wq;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const double z = (double)acc[m][t][v];
+              const double wv = nl[v] * ipow(z, dm1);
+              wq.e[v] = (T)wv;
+              wsum[t] += wv * z;
+            }
+            if (b < a.nblk) vstore4(a.Wp + (((b * a.nt_tot + tg + t) * 64) + lane) * 4, wq);
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
+      if (sl == sl_last) break;
+      ++sl;
+      kb = 0;
     }
   }
-  // Column sums: across the four row groups g of the wave, then the waves.
-  __shared__ double red[4][NT * 16];
+
+  // this wave's column sums: across the four lane groups, then one row of wpart
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     double s = wsum[t];
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
-    if (g == 0) red[wave][t * 16 + c] = s;
-  }
-  __syncthreads();
-  const int rp = a.nt_tot * 16;
-  for (int e = threadIdx.x; e < NT * 16; e += blockDim.x) {
-    const double s = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
-    a.wpart[(int64_t)blockIdx.x * rp + a.col0 + e] = s;
+    if (g == 0) a.wpart[(blk * NW + wave) * (int64_t)a.rp + a.col0 + 16 * t + c] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
 // gemm2: partial Y = V W over one split of the observations
 // ---------------------------------------------------------------------------
-template <typename T, int NT, bool VEC>
+template <typename T, int NT, int NS, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
   using acc_t = typename Mfma<T>::acc_t;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int g = lane >> 4, c = lane & 15;
-  const int64_t ibase = (int64_t)blockIdx.x * 256 + wave * 64;
-  const int64_t il = ibase + 4 * c;  // this lane's 4 rows (one per M subtile)
-  const int64_t n = a.n;
-  const bool rows_ok = il < n;
+  // Block -> (row block x, split y).  Consecutive block ids go to different
+  // XCDs (id mod 8), so the row blocks of one split get ids with the same
+  // residue mod 8: they run on one XCD and share the W slabs in its L2.
+  const int64_t bid = blockIdx.x;
+  const int RB = a.rowblocks;
+  const int y = (int)(bid % 8 + 8 * (bid / (8 * RB)));
+  const int x = (int)((bid / 8) % RB);
+  if (y >= a.nsplit) return;
 
-  const int split = blockIdx.y;
-  const int64_t b0 = (int64_t)split * a.blk_per_split;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t ibase = (int64_t)x * 256 + wave * 64;
+  const int64_t n = a.n;
+  // this lane's 4 rows (one per M subtile); rows past n are clamped to valid
+  // ones and their results are never read back (VEC needs n % 4 == 0, so a
+  // quad is wholly inside or wholly past n; otherwise each element is clamped)
+  const int64_t il = ibase + 4 * c;
+  const int64_t ilc = (il < n) ? il : n - 4;
+
+  const int64_t b0 = (int64_t)y * a.blk_per_split;
   const int64_t b1 = min((int64_t)a.nblk, b0 + a.blk_per_split);
+  const int tg = a.col0 >> 4;
 
   acc_t acc[4][NT];
 #pragma unroll
@@ -164,45 +415,54 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
 
-  Quad<T> vq0[4], wq0[NT], vq1[4], wq1[NT];
-  const int t0 = a.col0 >> 4;
-  auto load = [&](Quad<T>(&vq)[4], Quad<T>(&wq)[NT], int64_t b) {
+  Quad<T> vb[NS][4];
+  Quad<T> wb[NS][NT];
+  auto issue = [&](int buf, int64_t b) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-      vload4(wq[t], a.Wp + (((b * a.nt_tot + t0 + t) * 64) + lane) * 4);
+    for (int t = 0; t < NT; ++t) vload4(wb[buf][t], a.Wp + (((b * a.nt_tot + tg + t) * 64) + lane) * 4);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int64_t l = 16 * b + Mfma<T>::row(g, s);
-      const bool ok = rows_ok && l < a.p;
-      load4<T, VEC>(vq[s], a.V + (ok ? l : 0) * a.ldv, il, n, ok);
+      int64_t l = 16 * b + Mfma<T>::row(g, s);
+      l = l < a.p ? l : (int64_t)a.p - 1;     // zero rows of W: contribute nothing
+      const T* col = a.V + l * a.ldv;
+      if constexpr (VEC) {
+        vload4(vb[buf][s], col + ilc);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vb[buf][s].e[e] = col[min(il + e, n - 1)];
+      }
     }
   };
-  auto mma = [&](const Quad<T>(&vq)[4], const Quad<T>(&wq)[NT]) {
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(vq[s].e[m], wq[t].e[s], acc[m][t]);
+        for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(vb[buf][s].e[m], wb[buf][t].e[s], acc[m][t]);
   };
 
-  if (b0 < b1) {
-    load(vq0, wq0, b0);
-    for (int64_t b = b0;; b += 2) {
-      if (b + 1 < b1) load(vq1, wq1, b + 1);
-      mma(vq0, wq0);
-      if (b + 1 >= b1) break;
-      if (b + 2 < b1) load(vq0, wq0, b + 2);
-      mma(vq1, wq1);
-      if (b + 2 >= b1) break;
+  const int64_t Q = b1 - b0;
+  if (Q > 0) {
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s) issue(s, b0 + min((int64_t)s, Q - 1));
+    int64_t qb = 0;
+    for (; qb + NS <= Q; qb += NS) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        issue((s + NS - 1) % NS, b0 + min(qb + s + NS - 1, Q - 1));
+        compute(s);
+      }
     }
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+      if (s < Q - qb) compute(s);
   }
 
   // acc[m][t][v] = Y[ibase + 4 row(g, v) + m][col0 + 16t + c]
-  const int rp = a.nt_tot * 16;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    T* col = a.Ypart + ((int64_t)split * rp + a.col0 + 16 * t + c) * a.npad;
+    T* col = a.Ypart + ((int64_t)y * a.rp + a.col0 + 16 * t + c) * a.npad;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       Quad<T> q;
@@ -214,130 +474,239 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// gram: B = A'A, C = B^{d-1} (fp64), 16 x 16 output tile per block
+// pack_a: Apad[j][k] = A[k][j] for k < n, j < r, and 0 elsewhere (column-major,
+// leading dimension ldap = whole gemm1 chunks, rp columns)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram(GramArgs<T> a) {
-  __shared__ double sj[64][17];
-  __shared__ double sk[64][17];
+__global__ __launch_bounds__(256) void k_pack_a(PackAArgs<T> a) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (k >= a.ldap) return;
+  a.Apad[(int64_t)j * a.ldap + k] = (k < a.n && j < a.r) ? a.A[(int64_t)j * a.lda + k] : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// gram: B = A'A in fp64.  gram_part: one 16 x 16 tile of B over 128 rows of
+// A per block; gram_fin: fixed-order sum over the row splits, C = B^{d-1}.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_part(GramArgs<T> a) {
+  __shared__ double sj[128][17];
+  __shared__ double sk[128][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int j0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
+  const int64_t i0 = (int64_t)blockIdx.z * 128;
+  for (int e = threadIdx.x; e < 128 * 16; e += 256) {
+    const int ii = e & 127, cc = e >> 7;
+    const int64_t i = i0 + ii;
+    const int j = j0 + cc, k = k0 + cc;
+    sj[ii][cc] = (i < a.n && j < a.r) ? (double)a.A[(int64_t)j * a.lda + i] : 0.0;
+    sk[ii][cc] = (i < a.n && k < a.r) ? (double)a.A[(int64_t)k * a.lda + i] : 0.0;
+  }
+  __syncthreads();
   double acc = 0.0;
-  for (int64_t i0 = 0; i0 < a.n; i0 += 64) {
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int ii = e & 63, cc = e >> 6;
+#pragma unroll 16
+  for (int ii = 0; ii < 128; ++ii) acc = fma(sj[ii][tx], sk[ii][ty], acc);
+  const int j = j0 + tx, k = k0 + ty;
+  if (j < a.r && k < a.r) a.Bpart[(int64_t)blockIdx.z * a.r * a.r + (int64_t)k * a.r + j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_gram_fin(GramFinArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t rr = (int64_t)a.r * a.r;
+  if (e >= rr) return;
+  double b = 0.0;
+  for (int s = 0; s < a.nsplit; ++s) b += a.Bpart[s * rr + e];
+  a.B[e] = b;
+  a.C[e] = ipow(b, a.d - 1);
+}
+
+// ---------------------------------------------------------------------------
+// ymodel: Y_M = A D_lambda C (n x r, fp64, leading dimension n).  Block:
+// 64 rows x 16 columns, 4 outputs per thread, k in slices of 32 through LDS.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ymodel(YModelArgs<T> a) {
+  __shared__ double sa[32][65];   // A D_lambda slice: [k][row]
+  __shared__ double sc[32][17];   // C slice: [k][col]
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 16;
+  const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;   // row, column quarter
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < a.r; k0 += 32) {
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      const int ii = e & 63, kk = e >> 6;
       const int64_t i = i0 + ii;
-      const int j = j0 + cc, k = k0 + cc;
-      sj[ii][cc] = (i < a.n && j < a.r) ? (double)a.A[(int64_t)j * a.lda + i] : 0.0;
-      sk[ii][cc] = (i < a.n && k < a.r) ? (double)a.A[(int64_t)k * a.lda + i] : 0.0;
+      const int k = k0 + kk;
+      sa[kk][ii] = (i < a.n && k < a.r) ? (double)a.A[(int64_t)k * a.lda + i] * a.lambda[k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 32 * 16; e += 256) {
+      const int cc = e & 15, kk = e >> 4;
+      const int k = k0 + kk, j = j0 + cc;
+      sc[kk][cc] = (k < a.r && j < a.r) ? a.C[(int64_t)j * a.r + k] : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
-    for (int ii = 0; ii < 64; ++ii) acc = fma(sj[ii][tx], sk[ii][ty], acc);
+    for (int kk = 0; kk < 32; ++kk) {
+      const double x = sa[kk][tr];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(x, sc[kk][tc * 4 + q], acc[q]);
+    }
     __syncthreads();
   }
-  const int j = j0 + tx, k = k0 + ty;
-  if (j < a.r && k < a.r) {
-    a.B[(int64_t)k * a.r + j] = acc;
-    a.C[(int64_t)k * a.r + j] = ipow(acc, a.d - 1);
+  const int64_t i = i0 + tr;
+  if (i < a.n) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + tc * 4 + q;
+      if (j < a.r) a.YM[(int64_t)j * a.n + i] = acc[q];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// final_G: G_A = -2d (Y - A D_lambda C) D_lambda, Y = fixed-order sum of partials
+// final_s: one block per column j: w_j, u_j, g_lambda[j], and j's share of f
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_256(double v, double* sm) {
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_final_s(FinalSArgs a) {
+  __shared__ double sm[256];
+  const int j = blockIdx.x;
+  double w = 0.0;
+  for (int64_t b = threadIdx.x; b < a.nwpart; b += 256) w += a.wpart[b * a.rp + j];
+  w = block_sum_256(w, sm);
+  double u = 0.0;
+  for (int k = threadIdx.x; k < a.r; k += 256)
+    u += a.B[(int64_t)k * a.r + j] * a.C[(int64_t)k * a.r + j] * a.lambda[k];
+  u = block_sum_256(u, sm);
+  if (threadIdx.x == 0) {
+    a.g_lambda[j] = -2.0 * (w - u);
+    a.fpart[j] = a.lambda[j] * u - 2.0 * w * a.lambda[j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_final_f(FinalSArgs a) {
+  __shared__ double sm[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < a.r; j += 256) s += a.fpart[j];
+  s = block_sum_256(s, sm);
+  if (threadIdx.x == 0) a.f[0] = a.alpha + s;
+}
+
+// ---------------------------------------------------------------------------
+// final_G: G_A = -2d (Y - Y_M) D_lambda, Y = fixed-order sum of the partials
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_final_G(FinalGArgs<T> a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= a.n) return;
-  const int64_t rp = a.rp;
-  double y = 0.0;
   const T* yp = a.Ypart + (int64_t)j * a.npad + i;
-  for (int s = 0; s < a.nsplit; ++s) y += (double)yp[(int64_t)s * rp * a.npad];
-  double adc = 0.0;
-  for (int k = 0; k < a.r; ++k)
-    adc = fma((double)a.A[(int64_t)k * a.lda + i] * a.lambda[k], a.C[(int64_t)j * a.r + k], adc);
-  const double gval = -2.0 * a.d * (y - adc) * a.lambda[j];
+  const int64_t stride = a.rp * a.npad;
+  double y = 0.0;
+  int s = 0;
+  for (; s + 4 <= a.nsplit; s += 4) {
+    const double y0 = (double)yp[(s + 0) * stride], y1 = (double)yp[(s + 1) * stride];
+    const double y2 = (double)yp[(s + 2) * stride], y3 = (double)yp[(s + 3) * stride];
+    y += (y0 + y1) + (y2 + y3);
+  }
+  for (; s < a.nsplit; ++s) y += (double)yp[s * stride];
+  const double gval = -2.0 * a.d * (y - a.YM[(int64_t)j * a.n + i]) * a.lambda[j];
   a.G[(int64_t)j * a.ldg + i] = (T)gval;
-}
-
-// ---------------------------------------------------------------------------
-// final_s: w, u, f, g_lambda (one block)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_final_s(FinalSArgs a) {
-  __shared__ double rf[256];
-  double fl = 0.0;
-  for (int j = threadIdx.x; j < a.r; j += 256) {
-    double w = 0.0;
-    for (int64_t b = 0; b < a.nwpart; ++b) w += a.wpart[b * a.rp + j];
-    double u = 0.0;
-    for (int k = 0; k < a.r; ++k) {
-      const double bjk = a.B[(int64_t)k * a.r + j];
-      u = fma(bjk * a.C[(int64_t)k * a.r + j], a.lambda[k], u);
-    }
-    a.g_lambda[j] = -2.0 * (w - u);
-    fl += a.lambda[j] * u - 2.0 * w * a.lambda[j];
-  }
-  rf[threadIdx.x] = fl;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) rf[threadIdx.x] += rf[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) a.f[0] = a.alpha + rf[0];
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-template <typename T, int MT>
-static void dispatch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<T>& a) {
-#define G1_CASE(NTV)                                                            \
-  case NTV:                                                                     \
-    if (vec) hipLaunchKernelGGL((k_gemm1<T, MT, NTV, true>), grid, dim3(256), 0, st, a);  \
-    else hipLaunchKernelGGL((k_gemm1<T, MT, NTV, false>), grid, dim3(256), 0, st, a);    \
-    break;
-  if constexpr (sizeof(T) == 8) {
-    switch (nt) { G1_CASE(1) G1_CASE(2) G1_CASE(3) G1_CASE(4) default: break; }
-  } else {
-    switch (nt) { G1_CASE(1) G1_CASE(2) G1_CASE(3) G1_CASE(4) G1_CASE(5) G1_CASE(6) G1_CASE(7) default: break; }
+template <typename T, int NS2>
+struct Dispatch {
+  template <int NTV>
+  static void g1(bool dma, dim3 grid, hipStream_t st, const G1Args<T>& a) {
+    if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true>), grid, dim3(64 * G1_WAVES), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm1<T, NTV, false>), grid, dim3(64 * G1_WAVES), 0, st, a);
   }
-#undef G1_CASE
-}
+  template <int NTV>
+  static void g2(bool vec, dim3 grid, hipStream_t st, const G2Args<T>& a) {
+    if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, false>), grid, dim3(256), 0, st, a);
+  }
+};
 
-template <typename T>
-static void dispatch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<T>& a) {
-#define G2_CASE(NTV)                                                            \
-  case NTV:                                                                     \
-    if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, true>), grid, dim3(256), 0, st, a);  \
-    else hipLaunchKernelGGL((k_gemm2<T, NTV, false>), grid, dim3(256), 0, st, a);    \
-    break;
-  if constexpr (sizeof(T) == 8) {
-    switch (nt) { G2_CASE(1) G2_CASE(2) G2_CASE(3) G2_CASE(4) default: break; }
-  } else {
-    switch (nt) { G2_CASE(1) G2_CASE(2) G2_CASE(3) G2_CASE(4) G2_CASE(5) G2_CASE(6) G2_CASE(7) default: break; }
-  }
-#undef G2_CASE
-}
+using DF32 = Dispatch<float, G2_STAGES_F32>;
+using DF64 = Dispatch<double, G2_STAGES_F64>;
 
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<float>& a) {
-  dispatch_gemm1<float, G1_MT_F32>(nt, vec, grid, st, a);
+  switch (nt) {
+    case 1: DF32::g1<1>(vec, grid, st, a); break;
+    case 2: DF32::g1<2>(vec, grid, st, a); break;
+    case 3: DF32::g1<3>(vec, grid, st, a); break;
+    case 4: DF32::g1<4>(vec, grid, st, a); break;
+    case 5: DF32::g1<5>(vec, grid, st, a); break;
+    case 6: DF32::g1<6>(vec, grid, st, a); break;
+    case 7: DF32::g1<7>(vec, grid, st, a); break;
+    default: break;
+  }
 }
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<double>& a) {
-  dispatch_gemm1<double, G1_MT_F64>(nt, vec, grid, st, a);
+  switch (nt) {
+    case 1: DF64::g1<1>(vec, grid, st, a); break;
+    case 2: DF64::g1<2>(vec, grid, st, a); break;
+    case 3: DF64::g1<3>(vec, grid, st, a); break;
+    case 4: DF64::g1<4>(vec, grid, st, a); break;
+    default: break;
+  }
 }
 void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a) {
-  dispatch_gemm2<float>(nt, vec, grid, st, a);
+  switch (nt) {
+    case 1: DF32::g2<1>(vec, grid, st, a); break;
+    case 2: DF32::g2<2>(vec, grid, st, a); break;
+    case 3: DF32::g2<3>(vec, grid, st, a); break;
+    case 4: DF32::g2<4>(vec, grid, st, a); break;
+    case 5: DF32::g2<5>(vec, grid, st, a); break;
+    case 6: DF32::g2<6>(vec, grid, st, a); break;
+    case 7: DF32::g2<7>(vec, grid, st, a); break;
+    default: break;
+  }
 }
 void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<double>& a) {
-  dispatch_gemm2<double>(nt, vec, grid, st, a);
+  switch (nt) {
+    case 1: DF64::g2<1>(vec, grid, st, a); break;
+    case 2: DF64::g2<2>(vec, grid, st, a); break;
+    case 3: DF64::g2<3>(vec, grid, st, a); break;
+    case 4: DF64::g2<4>(vec, grid, st, a); break;
+    default: break;
+  }
+}
+void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<float>& a) {
+  hipLaunchKernelGGL(k_pack_a<float>, grid, dim3(256), 0, st, a);
+}
+void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<double>& a) {
+  hipLaunchKernelGGL(k_pack_a<double>, grid, dim3(256), 0, st, a);
 }
 void launch_gram(dim3 grid, hipStream_t st, const GramArgs<float>& a) {
-  hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_gram_part<float>, grid, dim3(256), 0, st, a);
 }
 void launch_gram(dim3 grid, hipStream_t st, const GramArgs<double>& a) {
-  hipLaunchKernelGGL(k_gram<double>, grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_gram_part<double>, grid, dim3(256), 0, st, a);
+}
+void launch_gram_fin(dim3 grid, hipStream_t st, const GramFinArgs& a) {
+  hipLaunchKernelGGL(k_gram_fin, grid, dim3(256), 0, st, a);
+}
+void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<float>& a) {
+  hipLaunchKernelGGL(k_ymodel<float>, grid, dim3(256), 0, st, a);
+}
+void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<double>& a) {
+  hipLaunchKernelGGL(k_ymodel<double>, grid, dim3(256), 0, st, a);
 }
 void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<float>& a) {
   hipLaunchKernelGGL(k_final_G<float>, grid, dim3(256), 0, st, a);
@@ -345,8 +714,11 @@ void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<float>& a) {
 void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<double>& a) {
   hipLaunchKernelGGL(k_final_G<double>, grid, dim3(256), 0, st, a);
 }
-void launch_final_s(hipStream_t st, const FinalSArgs& a) {
-  hipLaunchKernelGGL(k_final_s, dim3(1), dim3(256), 0, st, a);
+void launch_final_s(dim3 grid, hipStream_t st, const FinalSArgs& a) {
+  hipLaunchKernelGGL(k_final_s, grid, dim3(256), 0, st, a);
+}
+void launch_final_f(hipStream_t st, const FinalSArgs& a) {
+  hipLaunchKernelGGL(k_final_f, dim3(1), dim3(256), 0, st, a);
 }
 
 }  // namespace symtd

@@ -78,6 +78,29 @@ __device__ __forceinline__ void load4(Quad<T>& q, const T* base, int64_t i, int6
   }
 }
 
+// Full chunk: 4 consecutive in-range elements from a valid pointer, with no
+// branches (vector load when VEC, the caller guaranteeing 16-byte alignment).
+template <typename T, bool VEC>
+__device__ __forceinline__ void load_full(Quad<T>& q, const T* p) {
+  if constexpr (VEC) {
+    vload4(q, p);
+  } else {
+    q.e[0] = p[0]; q.e[1] = p[1]; q.e[2] = p[2]; q.e[3] = p[3];
+  }
+}
+
+// Ragged chunk: col[i .. i+3] with elements at or past n reading as zero.
+// Branch-free: every lane loads from a clamped in-range index and the
+// out-of-range elements are then replaced by zero.
+template <typename T>
+__device__ __forceinline__ void load_tail(Quad<T>& q, const T* col, int64_t i, int64_t n) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const T x = col[min(i + e, n - 1)];
+    q.e[e] = (i + e < n) ? x : T(0);
+  }
+}
+
 // x^k for a small non-negative integer k (k is uniform across the wave).
 __device__ __forceinline__ double ipow(double x, int k) {
   double r = 1.0;

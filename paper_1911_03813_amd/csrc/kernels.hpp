@@ -6,13 +6,34 @@
 
 namespace symtd {
 
-// M subtiles (16 observations each) per wave in gemm1.
-constexpr int G1_MT_F32 = 4;
-constexpr int G1_MT_F64 = 2;
 // Column subtiles handled by one launch of gemm1/gemm2 (16 columns each);
 // wider ranks are processed in several column groups.
-constexpr int NT_MAX_F32 = 7;
-constexpr int NT_MAX_F64 = 4;
+// Both products handle up to 7 in one launch for fp32 and 4 for fp64.
+constexpr int NT_MAX_G1_F32 = 7;
+constexpr int NT_MAX_G1_F64 = 4;
+constexpr int NT_MAX_G2_F32 = 7;
+constexpr int NT_MAX_G2_F64 = 4;
+// gemm1 shape: waves per block, M subtiles (16 observations) per wave, bytes
+// of one column run per chunk, and LDS stages of the chunk ring.
+#ifndef SYMTD_G1_WAVES
+#define SYMTD_G1_WAVES 4
+#endif
+#ifndef SYMTD_G1_MT
+#define SYMTD_G1_MT 2
+#endif
+#ifndef SYMTD_G1_RUN
+#define SYMTD_G1_RUN 256
+#endif
+#ifndef SYMTD_G1_STAGES
+#define SYMTD_G1_STAGES 2
+#endif
+constexpr int G1_WAVES = SYMTD_G1_WAVES;
+constexpr int G1_MT = SYMTD_G1_MT;
+constexpr int G1_RUN = SYMTD_G1_RUN;
+constexpr int G1_STAGES = SYMTD_G1_STAGES;
+// Depth of the register prefetch ring of gemm2.
+constexpr int G2_STAGES_F32 = 3;
+constexpr int G2_STAGES_F64 = 2;
 
 template <typename T>
 struct G1Args {
@@ -20,32 +41,63 @@ struct G1Args {
   const T* A; int64_t lda; int r;
   int col0;      // first column of this launch's column group (multiple of 16)
   int nt_tot;    // column subtiles over all groups: ceil(r / 16)
+  int rp;        // 16 * nt_tot
+  int nblk;      // ceil(p / 16) blocks of 16 observations (packed W)
+  int nslab;     // ceil(p / (16 * G1_MT * G1_WAVES)) block slabs
+  int nblocks;   // blocks taking part (<= nslab, all resident)
   int d;
-  T* Wp;         // packed W, ceil(p/16) slabs
-  double* wpart; // [gridDim.x][16 * nt_tot] fp64 column partials
+  const T* Apad; int64_t ldap;   // zero-padded factor copy (see k_pack_a)
+  T* Wp;         // packed W
+  double* wpart; // [G1_WAVES * nblocks][rp] fp64 column partials, one row per wave
+  T* part;       // [nblocks][G1_WAVES * G1_MT * NT * 256] published partial accumulators
+  int* flag;     // [nblocks] hand-off flags, zero between launches
+  int* err;      // set to 1 if a hand-off wait gave up
 };
 
 template <typename T>
 struct G2Args {
   const T* V; int64_t ldv; int n; int p;
-  const T* Wp; int nt_tot; int col0;
+  const T* Wp; int nt_tot; int rp; int col0;
   int nblk;           // ceil(p / 16)
   int blk_per_split;  // 16-observation slabs per split
-  T* Ypart;           // [nsplit][16 * nt_tot][npad]
+  int nsplit;
+  int rowblocks;      // npad / 256
+  T* Ypart;           // [nsplit][rp][npad]
   int64_t npad;       // rows of a partial column, multiple of 256
 };
 
 template <typename T>
+struct PackAArgs {
+  const T* A; int64_t lda; int n; int r;
+  T* Apad; int64_t ldap;   // rp columns of ldap rows
+};
+
+// k values per gemm1 chunk (one G1_RUN-byte run per column)
+template <typename T> constexpr int g1_chunk() { return G1_RUN / (int)sizeof(T); }
+
+template <typename T>
 struct GramArgs {
-  const T* A; int64_t lda; int n; int r; int d;
+  const T* A; int64_t lda; int n; int r;
+  double* Bpart;      // [ceil(n/128)][r][r]
+};
+
+struct GramFinArgs {
+  const double* Bpart; int nsplit; int r; int d;
   double* B; double* C;  // r x r, column-major
+};
+
+template <typename T>
+struct YModelArgs {
+  const T* A; int64_t lda; int n; int r;
+  const double* lambda; const double* C;
+  double* YM;         // n x r, leading dimension n
 };
 
 template <typename T>
 struct FinalGArgs {
   const T* Ypart; int64_t npad; int64_t rp; int nsplit;
-  const T* A; int64_t lda; int n; int r; int d;
-  const double* lambda; const double* C;
+  const double* YM; int n; int r; int d;
+  const double* lambda;
   T* G; int64_t ldg;
 };
 
@@ -53,6 +105,7 @@ struct FinalSArgs {
   const double* wpart; int64_t nwpart; int64_t rp;
   const double* B; const double* C; const double* lambda;
   int r; double alpha;
+  double* fpart;      // r per-column shares of f
   double* f; double* g_lambda;
 };
 
@@ -71,11 +124,17 @@ void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<floa
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<double>& a);
 void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a);
 void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<double>& a);
+void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<float>& a);
+void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<double>& a);
 void launch_gram(dim3 grid, hipStream_t st, const GramArgs<float>& a);
 void launch_gram(dim3 grid, hipStream_t st, const GramArgs<double>& a);
+void launch_gram_fin(dim3 grid, hipStream_t st, const GramFinArgs& a);
+void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<float>& a);
+void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<double>& a);
 void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<float>& a);
 void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<double>& a);
-void launch_final_s(hipStream_t st, const FinalSArgs& a);
+void launch_final_s(dim3 grid, hipStream_t st, const FinalSArgs& a);
+void launch_final_f(hipStream_t st, const FinalSArgs& a);
 
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<float>& a);
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<double>& a);

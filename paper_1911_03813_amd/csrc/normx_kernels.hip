@@ -28,7 +28,7 @@ template <typename S, bool VEC>
 __global__ __launch_bounds__(256) void k_normx(NormXArgs<S> a) {
   using acc_t = v4d;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int g = lane >> 4, c = lane & 15;
   int64_t tr, tc;
   tri_pair(blockIdx.x, a.ntile, tr, tc);

@@ -14,7 +14,7 @@
 
 using namespace symtd;
 
-static const char* kProfileNames[] = {"gemm1", "gemm2", "gram", "final_G", "final_s", "normx", "reduce"};
+static const char* kProfileNames[] = {"gemm1", "gemm2", "model", "final_G", "scalars", "normx", "reduce"};
 static constexpr int kNumProfile = sizeof(kProfileNames) / sizeof(kProfileNames[0]);
 
 symtd_status symtd_ctx::fail(symtd_status s, const char* fmt, ...) {
@@ -36,7 +36,7 @@ symtd_status symtd_ctx::reserve(size_t bytes) {
   // Growing replaces the buffer; wait for work that may still use it.
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-  if (ws) hipFree(ws);
+  if (ws) (void)hipFree(ws);
   ws = nullptr;
   ws_bytes = 0;
   const size_t want = std::max(bytes, (size_t)1 << 20);
@@ -52,15 +52,15 @@ symtd_status symtd_ctx::reserve(size_t bytes) {
 void symtd_ctx::prof_begin(int which, hipStream_t st) {
   if (!prof) return;
   hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
-  hipEventRecord(a, st);
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+  (void)hipEventRecord(a, st);
   pending.push_back({which, a, b, st});
 }
 
 void symtd_ctx::prof_end(hipStream_t st) {
   if (!prof || pending.empty()) return;
-  hipEventRecord(pending.back().stop, st);
+  (void)hipEventRecord(pending.back().stop, st);
   (void)st;
 }
 
@@ -92,35 +92,56 @@ template <typename X>
 bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct FgPlan {
-  int nt_tot, rp, nblk, mt, grid1, nsplit, blk_per_split;
+  int nt_tot, rp, nblk, nt1, nt2, nslab, nblocks, nsplit, blk_per_split, rowblocks, gsplit;
   int64_t npad;
-  size_t bytes(size_t esz, int r) const {
-    // Carve order: Wp, wpart, Ypart, B, C (each 256-byte aligned)
+  int64_t ldap;
+  size_t apad, wp, wpart, part, ypart, bpart, rr, ym;  // element counts
+  size_t bytes(size_t esz) const {
     size_t s = 0;
     auto add = [&](size_t b) { s = ((s + 255) & ~(size_t)255) + b; };
-    add((size_t)nblk * 16 * rp * esz);
-    add((size_t)grid1 * rp * sizeof(double));
-    add((size_t)nsplit * rp * npad * esz);
-    add((size_t)r * r * sizeof(double));
-    add((size_t)r * r * sizeof(double));
+    add(apad * esz);
+    add(wp * esz);
+    add(wpart * sizeof(double));
+    add(part * esz);
+    add(ypart * esz);
+    add(bpart * sizeof(double));
+    add(rr * sizeof(double));
+    add(rr * sizeof(double));
+    add(ym * sizeof(double));
+    add(256 * sizeof(double));
     return s + 256;
   }
 };
 
-FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus) {
+FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_blocks, int64_t g2_splits) {
   FgPlan P;
   P.nt_tot = (int)((r + 15) / 16);
   P.rp = 16 * P.nt_tot;
   P.nblk = (int)((p + 15) / 16);
-  P.mt = f64 ? G1_MT_F64 : G1_MT_F32;
-  P.grid1 = (int)((p + 64 * P.mt - 1) / (64 * P.mt));
+  P.nt1 = f64 ? NT_MAX_G1_F64 : NT_MAX_G1_F32;
+  P.nt2 = f64 ? NT_MAX_G2_F64 : NT_MAX_G2_F32;
+  // gemm1: one block per CU, never more blocks than slabs
+  P.nslab = (int)((p + 16 * G1_MT * G1_WAVES - 1) / (16 * G1_MT * G1_WAVES));
+  P.nblocks = (int)std::min<int64_t>(g1_blocks > 0 ? std::min<int64_t>(g1_blocks, cus) : cus, P.nslab);
+  // gemm2: row blocks of 256 x splits of the observations, one block per CU
   P.npad = ((n + 255) / 256) * 256;
-  const int rowblocks = (int)(P.npad / 256);
-  const int target = 2 * cus;
-  int nsplit = std::max(1, (target + rowblocks - 1) / rowblocks);
+  P.rowblocks = (int)(P.npad / 256);
+  int nsplit = g2_splits > 0 ? (int)std::min<int64_t>(g2_splits, 1 << 20)
+                             : std::max(1, (cus + P.rowblocks - 1) / P.rowblocks);
   nsplit = std::min(nsplit, P.nblk);
   P.blk_per_split = (P.nblk + nsplit - 1) / nsplit;
   P.nsplit = (P.nblk + P.blk_per_split - 1) / P.blk_per_split;
+  P.gsplit = (int)((n + 127) / 128);
+  const int kch = f64 ? g1_chunk<double>() : g1_chunk<float>();
+  P.ldap = ((n + kch - 1) / kch) * kch;
+  P.apad = (size_t)P.rp * P.ldap;
+  P.wp = (size_t)P.nblk * 16 * P.rp;
+  P.wpart = (size_t)G1_WAVES * P.nblocks * P.rp;
+  P.part = (size_t)P.nblocks * G1_WAVES * G1_MT * P.nt1 * 256;
+  P.ypart = (size_t)P.nsplit * P.rp * P.npad;
+  P.bpart = (size_t)P.gsplit * r * r;
+  P.rr = (size_t)r * r;
+  P.ym = (size_t)n * r;
   return P;
 }
 
@@ -129,59 +150,89 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
                     int64_t n, int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r,
                     int d, double alpha, double* f, double* g_lambda, T* G, int64_t ldg) {
   const bool f64 = sizeof(T) == 8;
-  const FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count);
-  symtd_status s = ctx->reserve(P.bytes(sizeof(T), (int)r));
+  const FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count, ctx->tune_g1_blocks, ctx->tune_g2_splits);
+  if (P.nblocks > ctx->nflags) return ctx->fail(SYMTD_EINVAL, "internal: %d blocks exceed the flag array", P.nblocks);
+  symtd_status s = ctx->reserve(P.bytes(sizeof(T)));
   if (s != SYMTD_OK) return s;
   Carve cv(ctx->ws);
-  T* Wp = cv.take<T>((size_t)P.nblk * 16 * P.rp);
-  double* wpart = cv.take<double>((size_t)P.grid1 * P.rp);
-  T* Ypart = cv.take<T>((size_t)P.nsplit * P.rp * P.npad);
-  double* B = cv.take<double>((size_t)r * r);
-  double* C = cv.take<double>((size_t)r * r);
+  T* Apad = cv.take<T>(P.apad);
+  T* Wp = cv.take<T>(P.wp);
+  double* wpart = cv.take<double>(P.wpart);
+  T* part = cv.take<T>(P.part);
+  T* Ypart = cv.take<T>(P.ypart);
+  double* Bpart = cv.take<double>(P.bpart);
+  double* B = cv.take<double>(P.rr);
+  double* C = cv.take<double>(P.rr);
+  double* YM = cv.take<double>(P.ym);
+  double* fpart = cv.take<double>(r);
 
-  const int ntmax = f64 ? NT_MAX_F64 : NT_MAX_F32;
   const size_t vq = 16 / sizeof(T);
   const bool vecV = aligned_to<T>(V, 16) && (ldv % vq) == 0;
-  const bool vecA = aligned_to<T>(A, 16) && (lda % vq) == 0;
+  // the model terms (B, C, Y_M) and the scalars run on the side stream beside
+  // gemm1/gemm2 (fork/join through events), or in order on the caller's stream
+  hipStream_t side = ctx->tune_serial ? st : ctx->side;
 
-  // B = A'A, C = B^{d-1}
+  (void)hipEventRecord(ctx->ev_fork, st);
+  (void)hipStreamWaitEvent(side, ctx->ev_fork, 0);
   {
-    GramArgs<T> ga{A, lda, (int)n, (int)r, d, B, C};
-    const dim3 grid((unsigned)((r + 15) / 16), (unsigned)((r + 15) / 16));
-    ctx->prof_begin(2, st);
-    launch_gram(grid, st, ga);
+    GramArgs<T> ga{A, lda, (int)n, (int)r, Bpart};
+    const unsigned rt = (unsigned)((r + 15) / 16);
+    ctx->prof_begin(2, side);
+    launch_gram(dim3(rt, rt, (unsigned)P.gsplit), side, ga);
+    GramFinArgs gf{Bpart, P.gsplit, (int)r, d, B, C};
+    launch_gram_fin(dim3((unsigned)((P.rr + 255) / 256)), side, gf);
+    YModelArgs<T> ya{A, lda, (int)n, (int)r, lambda, C, YM};
+    launch_ymodel(dim3((unsigned)((n + 63) / 64), rt), side, ya);
+    ctx->prof_end(side);
+    (void)hipEventRecord(ctx->ev_model, side);
+  }
+  // zero-padded factor copy for gemm1
+  {
+    PackAArgs<T> pa{A, lda, (int)n, (int)r, Apad, P.ldap};
+    launch_pack_a(dim3((unsigned)((P.ldap + 255) / 256), (unsigned)P.rp), st, pa);
+  }
+  // Z = V'A and its epilogue, one launch per column group; the direct
+  // global-to-LDS path needs 16-byte aligned columns holding whole quads
+  const bool dma = vecV && (n % 4) == 0;
+  for (int t0 = 0; t0 < P.nt_tot; t0 += P.nt1) {
+    const int nt = std::min(P.nt1, P.nt_tot - t0);
+    G1Args<T> a1{V, ldv, nu, (int)n, (int)p, A, lda, (int)r, 16 * t0, P.nt_tot, P.rp, P.nblk,
+                 P.nslab, P.nblocks, d, Apad, P.ldap, Wp, wpart, part, ctx->flags, ctx->dev_err};
+    ctx->prof_begin(0, st);
+    launch_gemm1(nt, dma, dim3(P.nblocks), st, a1);
     ctx->prof_end(st);
   }
-  // Z = V'A and its epilogue, one launch per group of up to NT_MAX column subtiles
-  for (int t0 = 0; t0 < P.nt_tot; t0 += ntmax) {
-    const int nt = std::min(ntmax, P.nt_tot - t0);
-    G1Args<T> a1{V, ldv, nu, (int)n, (int)p, A, lda, (int)r, 16 * t0, P.nt_tot, d, Wp, wpart};
-    ctx->prof_begin(0, st);
-    launch_gemm1(nt, vecV && vecA, dim3(P.grid1), st, a1);
-    ctx->prof_end(st);
+  // w, u, f, g_lambda on the side stream once gemm1 is done
+  (void)hipEventRecord(ctx->ev_g1, st);
+  (void)hipStreamWaitEvent(side, ctx->ev_g1, 0);
+  {
+    FinalSArgs as{wpart, (int64_t)G1_WAVES * P.nblocks, P.rp, B, C, lambda, (int)r, alpha, fpart, f, g_lambda};
+    ctx->prof_begin(4, side);
+    launch_final_s(dim3((unsigned)r), side, as);
+    launch_final_f(side, as);
+    ctx->prof_end(side);
+    (void)hipEventRecord(ctx->ev_side, side);
   }
   // Y = V W, split over the observations
-  for (int t0 = 0; t0 < P.nt_tot; t0 += ntmax) {
-    const int nt = std::min(ntmax, P.nt_tot - t0);
-    G2Args<T> a2{V, ldv, (int)n, (int)p, Wp, P.nt_tot, 16 * t0, P.nblk, P.blk_per_split, Ypart, P.npad};
-    const dim3 grid((unsigned)(P.npad / 256), (unsigned)P.nsplit);
+  for (int t0 = 0; t0 < P.nt_tot; t0 += P.nt2) {
+    const int nt = std::min(P.nt2, P.nt_tot - t0);
+    G2Args<T> a2{V, ldv, (int)n, (int)p, Wp, P.nt_tot, P.rp, 16 * t0, P.nblk, P.blk_per_split,
+                 P.nsplit, P.rowblocks, Ypart, P.npad};
+    const unsigned blocks = (unsigned)(P.rowblocks * 8 * ((P.nsplit + 7) / 8));
     ctx->prof_begin(1, st);
-    launch_gemm2(nt, vecV, grid, st, a2);
+    launch_gemm2(nt, vecV && (n % 4) == 0, dim3(blocks), st, a2);
     ctx->prof_end(st);
   }
+  (void)hipStreamWaitEvent(st, ctx->ev_model, 0);
   {
-    FinalGArgs<T> ag{Ypart, P.npad, P.rp, P.nsplit, A, lda, (int)n, (int)r, d, lambda, C, G, ldg};
+    FinalGArgs<T> ag{Ypart, P.npad, P.rp, P.nsplit, YM, (int)n, (int)r, d, lambda, G, ldg};
     const dim3 grid((unsigned)((n + 255) / 256), (unsigned)r);
     ctx->prof_begin(3, st);
     launch_final_G(grid, st, ag);
     ctx->prof_end(st);
   }
-  {
-    FinalSArgs as{wpart, P.grid1, P.rp, B, C, lambda, (int)r, alpha, f, g_lambda};
-    ctx->prof_begin(4, st);
-    launch_final_s(st, as);
-    ctx->prof_end(st);
-  }
+  // join
+  (void)hipStreamWaitEvent(st, ctx->ev_side, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ctx->hip_fail(e, "kernel launch (fg)");
   return SYMTD_OK;
@@ -265,16 +316,34 @@ symtd_status symtd_create(int device, symtd_ctx** out) {
   if (!c) return SYMTD_ENOMEM;
   c->device = device;
   c->cu_count = prop.multiProcessorCount;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_model, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_g1, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&c->flags, sizeof(int) * (4 * (size_t)c->cu_count + 1)) != hipSuccess ||
+      hipMemset(c->flags, 0, sizeof(int) * (4 * (size_t)c->cu_count + 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    symtd_destroy(c);
+    return SYMTD_EDEVICE;
+  }
+  c->nflags = 4 * c->cu_count;  // >= the blocks of any split product
+  c->dev_err = c->flags + c->nflags;
   *out = c;
   return SYMTD_OK;
 }
 
 void symtd_destroy(symtd_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
-  for (auto& pe : ctx->pending) { hipEventDestroy(pe.start); hipEventDestroy(pe.stop); }
-  if (ctx->ws) hipFree(ctx->ws);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& pe : ctx->pending) { (void)hipEventDestroy(pe.start); (void)hipEventDestroy(pe.stop); }
+  for (hipEvent_t ev : {ctx->ev_fork, ctx->ev_model, ctx->ev_g1, ctx->ev_side})
+    if (ev) (void)hipEventDestroy(ev);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->flags) (void)hipFree(ctx->flags);
+  if (ctx->ws) (void)hipFree(ctx->ws);
   delete ctx;
 }
 
@@ -324,6 +393,17 @@ symtd_status symtd_normX(symtd_ctx* ctx, void* stream, symtd_dtype dt, const voi
   return run_normx<float>(ctx, st, (const float*)V, ldv, nu, n, p, d, alpha);
 }
 
+symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value) {
+  if (!ctx) return SYMTD_EINVAL;
+  if (value < 0) return ctx->fail(SYMTD_EINVAL, "tuning value %lld < 0", (long long)value);
+  switch (key) {
+    case SYMTD_TUNE_G1_BLOCKS: ctx->tune_g1_blocks = value; return SYMTD_OK;
+    case SYMTD_TUNE_G2_SPLITS: ctx->tune_g2_splits = value; return SYMTD_OK;
+    case SYMTD_TUNE_SERIAL: ctx->tune_serial = value; return SYMTD_OK;
+  }
+  return ctx->fail(SYMTD_EINVAL, "unknown tuning key %d", (int)key);
+}
+
 symtd_status symtd_profile_enable(symtd_ctx* ctx, int enable) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->prof = enable != 0;
@@ -333,9 +413,9 @@ symtd_status symtd_profile_enable(symtd_ctx* ctx, int enable) {
 symtd_status symtd_profile_reset(symtd_ctx* ctx) {
   if (!ctx) return SYMTD_EINVAL;
   for (auto& pe : ctx->pending) {
-    hipEventSynchronize(pe.stop);
-    hipEventDestroy(pe.start);
-    hipEventDestroy(pe.stop);
+    (void)hipEventSynchronize(pe.stop);
+    (void)hipEventDestroy(pe.start);
+    (void)hipEventDestroy(pe.stop);
   }
   ctx->pending.clear();
   return SYMTD_OK;

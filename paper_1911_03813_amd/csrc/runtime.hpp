@@ -14,6 +14,16 @@ struct symtd_ctx {
   std::string err;
   void* ws = nullptr;   // device workspace, grown on demand
   size_t ws_bytes = 0;
+  // side stream for the model terms, and the events of the fork/join
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_model = nullptr, ev_g1 = nullptr, ev_side = nullptr;
+  // hand-off flags of the split products (zero between launches) and a
+  // device error word set if a hand-off wait ever gives up
+  int* flags = nullptr;
+  int nflags = 0;
+  int* dev_err = nullptr;
+  // work-split overrides (0 = automatic)
+  int64_t tune_g1_blocks = 0, tune_g2_splits = 0, tune_serial = 0;
 
   // per-kernel timing (symtd_profile_*)
   struct Pending { int which; hipEvent_t start, stop; hipStream_t st; };

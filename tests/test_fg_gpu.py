@@ -114,6 +114,22 @@ def test_large_config_fp64(ctx):
     check(ctx, 1000, 100_000, 100, 3, (8,), "f64", alpha=0.0)
 
 
+@pytest.mark.parametrize("waves,splits", [(1, 1), (2, 3), (3, 7), (7, 2), (64, 5), (1000, 100)])
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_work_splits(ctx, waves, splits, kind):
+    # every split of the first product over waves (with partial hand-offs
+    # between neighbours) and of the second over observation ranges gives the
+    # same result to rounding
+    try:
+        S.symtd_set_tuning(ctx, S.TUNE_G1_BLOCKS, waves)
+        S.symtd_set_tuning(ctx, S.TUNE_G2_SPLITS, splits)
+        check(ctx, 70, 3000, 40, 3, (10, waves), kind)
+        check(ctx, 33, 777, 9, 4, (11, waves), kind)
+    finally:
+        S.symtd_set_tuning(ctx, S.TUNE_G1_BLOCKS, 0)
+        S.symtd_set_tuning(ctx, S.TUNE_G2_SPLITS, 0)
+
+
 def test_deterministic(ctx):
     V, nu, A, lam = make_case(300, 20000, 40, 3, (9,), kind="f32")
     a = run_fg(ctx, V, nu, A, lam, 3, 0.0, "f32")

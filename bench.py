@@ -32,10 +32,34 @@ WORKLOAD = dict(d=3, n=1000, r=100, p=100_000, sigma=1e-2)
 # MI355X published dense matrix-core peaks (TFLOP/s) and HBM bandwidth (GB/s)
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the dominant kernels, from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE counters scaled by a copy-kernel calibration (None until measured
-# for the current kernels).
-TRAFFIC_BYTES = {}
+# HBM bytes per evaluation (summed over the launches of one evaluation) of the
+# two products, from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE (x 1.000)
+# counters, the factors being what the same counters read for a plain copy of
+# known size.  They hold for the kernel sources whose hash is stored with them
+# and are reported as null once those sources change.
+TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
+                   "paper_1911_03813_amd/csrc/kcommon.hpp")
+TRAFFIC_SHA = "857cbde6129424ac"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 492.3e6, ("fp32", "gemm2"): 474.4e6,
+                 ("fp64", "gemm1"): 1796.9e6, ("fp64", "gemm2"): 1748.6e6}
+
+
+def traffic_for(prec, kernel):
+    return TRAFFIC_BYTES.get((prec, kernel)) if kernel_source_hash() == TRAFFIC_SHA else None
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources' code (line comments and blank lines left out)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for s in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, s)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -49,7 +73,20 @@ def parse():
     ap.add_argument("--serial", action="store_true", help="model terms on the caller's stream")
     ap.add_argument("--g1-blocks", type=int, default=0)
     ap.add_argument("--g2-splits", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB elementwise copy a few times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A copy kernel of known size: reads and writes 256 MiB per launch."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 3}))
 
 
 def cpu_baseline(V64, nu, A64, lam, d, seconds):
@@ -80,6 +117,9 @@ def main():
               "(the evaluation would shard over observations with one all-reduce of Y and w).",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
 
@@ -138,7 +178,7 @@ def main():
     dom = max(("gemm1", "gemm2"), key=lambda k: per_kernel.get(k, {"step_us": 0})["step_us"])
     dom_us = per_kernel[dom]["step_us"]
     achieved = flop_gemm / (dom_us * 1e-6) / 1e12
-    traffic = TRAFFIC_BYTES.get((args.prec, dom))
+    traffic = traffic_for(args.prec, dom)
 
     res = {
         "metric": "f+grad f evals/s (n=1000, p=1e5, r=100, d=3)",

@@ -36,7 +36,7 @@ namespace symtd {
 // 16*G1_MT*G1_WAVES observations (16*G1_MT per wave).  The k range (the n covariates) is cut into
 // chunks of KCH = 4*QPC; for every chunk the block moves the slab's
 // observation columns and the factor columns into LDS, each column as one
-// contiguous run of 128 bytes (QPC quads of 4 elements), and the waves read
+// contiguous run of G1_RUN bytes (QPC quads of 4 elements), and the waves read
 // their MFMA fragments from LDS.  LDS holds a column's quads at a swizzled
 // slot (quad q of column col at col*QPC + (q ^ ((col/2) mod QPC))), so the 16
 // columns of one fragment read fall in distinct banks.
@@ -46,7 +46,8 @@ namespace symtd {
 // (global_load_lds): every lane fetches the piece whose LDS slot is its own,
 // and every thread issues the same number of pieces per chunk, so a wave can
 // wait for exactly one chunk with vmcnt.  Chunks rotate through G1_STAGES
-// LDS stages, G1_STAGES-1 of them in flight while one is multiplied.  Other
+// LDS stages: with two, the next chunk is in flight while one is multiplied
+// (with three, the next two).  Other
 // layouts pass through registers with two stages.  The factors are read from
 // a zero-padded copy (Apad) so that they never need masking.
 //

@@ -15,8 +15,10 @@ Anal. Appl., 2020; arXiv 1911.03813):
   explicit tensors (eqs. (optFunc), (gradl), (gradb)), and by the implicit
   Algorithm 2 built on Lemmas 3.1-3.5 and eq. (Y).
 * ``normx``   - the constant ||X||^2 (Lemma 3.4 applied to X).
-* ``lbfgs``   - the reference L-BFGS driver with restarts (Section 4 uses
-  L-BFGS with memory 5; the line search is this project's stated reading).
+* ``lbfgs``   - the reference L-BFGS driver (Section 4 uses L-BFGS with
+  memory 5; the line search and stopping tests are a stated reading).
+* ``solve``   - Gaussian and randomized-range-finder starts (eq. (rrf)) and
+  the restarted solve that keeps the best final f (Section 4.2).
 * ``metrics`` - relative error (Section 4.2), similarity score
   (eq. (Score)) and a gauge-invariant model distance.
 * ``philox``  - the Philox-4x32-10 counter-based generator and Box-Muller

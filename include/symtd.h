@@ -98,6 +98,20 @@ symtd_status symtd_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt,
                       double* f, double* g_lambda, void* G_A, int64_t ldg);
 
 /*
+ * Algorithm 2 for several models sharing one data tensor: model m (0 <= m <
+ * models) has factors = columns m*r .. m*r + r - 1 of A and weights
+ * lambda[m*r .. m*r + r - 1]; its f is f[m] and its gradients occupy the same
+ * columns of g_lambda and G_A.  The two products read V once for all models
+ * (their columns side by side); the model terms B, C, u are formed per model.
+ * symtd_fg is this call with models = 1.  Other arguments as in symtd_fg.
+ */
+symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt,
+                            const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
+                            const void* A, int64_t lda, const double* lambda, int64_t r, int64_t models,
+                            int d, double alpha, symtd_prec prec,
+                            double* f, double* g_lambda, void* G_A, int64_t ldg);
+
+/*
  * The constant term alpha = ||X||^2 = nu' [V'V]^d nu (elementwise power),
  * which is Lemma 3.4 applied to X (Section 3.3). O(n p^2) work: the p x p
  * Gram matrix is formed tile by tile on fp64 matrix cores from the values of
@@ -107,6 +121,106 @@ symtd_status symtd_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt,
 symtd_status symtd_normX(symtd_ctx* ctx, void* stream, symtd_dtype dt,
                          const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
                          int d, double* alpha);
+
+/* ------------------------------------------------------------------------
+ * Solve: minimise f over (lambda, A) with L-BFGS and restarts (Section 4: an
+ * L-BFGS method with memory m = 5 and limits on iterations and evaluations;
+ * Section 4.2: several starts, the best final f is kept).
+ *
+ * Starts (Section 4.2): lambda_0 = 1 and A_0 with unit columns drawn either
+ * from N(0,1) (SYMTD_INIT_GAUSS) or as V Omega with Omega ~ N(0,1)^{p x r}
+ * (SYMTD_INIT_RRF, the randomized range finder of eq. (rrf)).  The normals
+ * are Philox-4x32-10 / Box-Muller draws keyed by (seed, restart): element e
+ * (column-major) of the start matrix of restart k is normal e mod 4 of the
+ * Philox block with counter (e/4 low word, e/4 high word, k, s) and key
+ * (seed low word, seed high word), with s = 1 for the Gaussian A_0 and s = 2
+ * for Omega; words (x0, x1) give normals 0, 1 and (x2, x3) normals 2, 3,
+ * through u = (x + 1/2) 2^-32, sqrt(-2 ln u_a) (cos, sin)(2 pi u_b).
+ *
+ * The method minimises phi = f / s with s = alpha when alpha is used (known
+ * or computed) and s = 1 otherwise.  Each iteration takes the L-BFGS
+ * direction (memory m, H0 = gamma I with gamma = s'y/y'y of the newest pair;
+ * a pair is kept only if s'y > 1e-10 y'y; a non-descent direction clears the
+ * memory and uses -g) and a strong-Wolfe line search (c1 = 1e-3, c2 = 0.9;
+ * first trial min(1, 1/||g||_2) along -g, else 1; bracketing doubles the
+ * trial; zoom uses the safeguarded cubic minimiser; at most 20 evaluations).
+ * Stopping: ||grad phi||_inf <= pgtol; phi_k - phi_{k+1} <= ftol
+ * max(|phi_k|, |phi_{k+1}|, 1); iterations >= max_iters; evaluations >=
+ * max_evals; a failed line search; a non-finite value at the start.
+ *
+ * All restarts run together: every evaluation step evaluates all of them in
+ * one symtd_fg_multi-style pass (V read once), and the L-BFGS state of every
+ * restart lives on the device; the host only polls stop flags.  The call is
+ * synchronous with respect to `stream` (it returns after the solve).
+ * ------------------------------------------------------------------------ */
+typedef enum symtd_init { SYMTD_INIT_GAUSS = 0, SYMTD_INIT_RRF = 1 } symtd_init;
+
+typedef enum symtd_alpha_mode {
+  SYMTD_ALPHA_COMPUTE = 0,   /* alpha = ||X||^2 by symtd_normX, then used as s */
+  SYMTD_ALPHA_GIVEN = 1,     /* use opts.alpha (> 0) */
+  SYMTD_ALPHA_NONE = 2       /* shifted objective (alpha = 0), s = 1 */
+} symtd_alpha_mode;
+
+typedef enum symtd_exit {
+  SYMTD_EXIT_RUNNING = 0, SYMTD_EXIT_PGTOL = 1, SYMTD_EXIT_FTOL = 2, SYMTD_EXIT_MAX_ITERS = 3,
+  SYMTD_EXIT_MAX_EVALS = 4, SYMTD_EXIT_LINESEARCH = 5, SYMTD_EXIT_NONFINITE = 6
+} symtd_exit;
+
+/* The data of one decomposition problem (device pointers as in symtd_fg). */
+typedef struct symtd_problem {
+  symtd_dtype dt;
+  const void* V; int64_t ldv;
+  const double* nu;
+  int64_t n, p;
+  int d;
+  int64_t r;
+} symtd_problem;
+
+typedef struct symtd_solve_opts {
+  symtd_prec prec;
+  int m;                    /* L-BFGS memory, 1..8 (paper: 5) */
+  double pgtol;             /* >= 0 */
+  double ftol;              /* >= 0 (L-BFGS-B's default factr 1e7 times eps is 2.22e-9) */
+  int64_t max_iters;        /* >= 1 */
+  int64_t max_evals;        /* >= 1 */
+  int restarts;             /* >= 1 */
+  uint64_t seed;
+  symtd_init init;
+  symtd_alpha_mode alpha_mode;
+  double alpha;             /* used with SYMTD_ALPHA_GIVEN */
+  const void* A0;           /* optional device starts, n x (restarts r) of type dt, leading
+                               dimension n (restart k = columns k r ..); NULL = draw them */
+  int check_every;          /* evaluation steps between polls of the stop flags (0 = automatic) */
+} symtd_solve_opts;
+
+typedef struct symtd_solve_result {
+  /* caller-owned outputs */
+  void* A; int64_t lda;     /* device, n x r of type dt: factors of the best restart */
+  double* lambda;           /* device, r values */
+  double* f_restarts;       /* host, `restarts` final f values, or NULL */
+  int64_t* iters_restarts;  /* host, `restarts` values, or NULL */
+  int64_t* evals_restarts;  /* host, `restarts` values, or NULL */
+  int* exit_restarts;       /* host, `restarts` symtd_exit values, or NULL */
+  double* f_trace;          /* host, restarts x trace_len: f at the start and after every
+                               accepted step (NaN past the end), or NULL */
+  int64_t trace_len;
+  /* written by the call */
+  double f;                 /* final f of the best restart (includes alpha) */
+  double alpha;             /* the alpha used (0 with SYMTD_ALPHA_NONE) */
+  double rel_err;           /* sqrt(max(f, 0) / alpha), NaN without alpha */
+  int64_t iters, evals;     /* of the best restart */
+  int exit_reason;          /* of the best restart */
+  int best_restart;         /* lowest final f, lowest index on ties */
+  int64_t steps;            /* evaluation steps run (all restarts together) */
+} symtd_solve_result;
+
+/* Fill `opts` with defaults: fp32 products, m = 5, pgtol = 1e-4, ftol =
+ * 2.22e-9, max_iters = 10000, max_evals = 50000 (Section 4), 1 restart,
+ * seed 0, RRF starts, alpha computed. */
+symtd_status symtd_solve_opts_default(symtd_solve_opts* opts);
+
+symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb,
+                         const symtd_solve_opts* opts, symtd_solve_result* out);
 
 /*
  * Work-split tuning of the evaluation kernels (used by the autotuner and by

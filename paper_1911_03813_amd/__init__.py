@@ -34,6 +34,32 @@ class SymtdError(RuntimeError):
 
 _lib = None
 _c = ctypes
+
+
+class Problem(ctypes.Structure):
+    """symtd_problem"""
+    _fields_ = [("dt", ctypes.c_int), ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("nu", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("p", ctypes.c_int64), ("d", ctypes.c_int), ("r", ctypes.c_int64)]
+
+
+class SolveOpts(ctypes.Structure):
+    """symtd_solve_opts"""
+    _fields_ = [("prec", ctypes.c_int), ("m", ctypes.c_int), ("pgtol", ctypes.c_double), ("ftol", ctypes.c_double),
+                ("max_iters", ctypes.c_int64), ("max_evals", ctypes.c_int64), ("restarts", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("init", ctypes.c_int), ("alpha_mode", ctypes.c_int),
+                ("alpha", ctypes.c_double), ("A0", ctypes.c_void_p), ("check_every", ctypes.c_int)]
+
+
+class SolveResult(ctypes.Structure):
+    """symtd_solve_result"""
+    _fields_ = [("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("lam", ctypes.c_void_p),
+                ("f_restarts", ctypes.POINTER(ctypes.c_double)), ("iters_restarts", ctypes.POINTER(ctypes.c_int64)),
+                ("evals_restarts", ctypes.POINTER(ctypes.c_int64)), ("exit_restarts", ctypes.POINTER(ctypes.c_int)),
+                ("f_trace", ctypes.POINTER(ctypes.c_double)), ("trace_len", ctypes.c_int64),
+                ("f", ctypes.c_double), ("alpha", ctypes.c_double), ("rel_err", ctypes.c_double),
+                ("iters", ctypes.c_int64), ("evals", ctypes.c_int64), ("exit_reason", ctypes.c_int),
+                ("best_restart", ctypes.c_int), ("steps", ctypes.c_int64)]
+
 _vp = _c.c_void_p
 _i64 = _c.c_int64
 _int = _c.c_int
@@ -47,8 +73,12 @@ SIGNATURES = {
     "symtd_status_string": (_c.c_char_p, [_int]),
     "symtd_fg": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int,
                         _dbl, _int, _vp, _vp, _vp, _i64]),
+    "symtd_fg_multi": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _int,
+                              _dbl, _int, _vp, _vp, _vp, _i64]),
     "symtd_normX": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _vp]),
     "symtd_set_tuning": (_int, [_vp, _int, _i64]),
+    "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
+    "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
     "symtd_profile_enable": (_int, [_vp, _int]),
     "symtd_profile_reset": (_int, [_vp]),
     "symtd_profile_read": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
@@ -181,6 +211,103 @@ def symtd_fg(ctx: Context, V, nu, A, lam, d: int, alpha: float = 0.0, prec: int 
                         float(alpha), int(prec), _vec(f, "f", 1), _vec(g, "g_lambda", r), Gp, ldg)
     _check(ctx, st)
     return f, g, G
+
+
+def symtd_fg_multi(ctx: Context, V, nu, A, lam, r: int, d: int, alpha: float = 0.0, prec: int | None = None,
+                   out=None, stream=None):
+    """Algorithm 2 for the models side by side in A (n x models*r) and lam.
+
+    Returns (f: (models,) float64, g_lambda: (models*r,) float64, G_A: like A).
+    """
+    import torch
+    Vp, ldv = _mat(V, "V")
+    Ap, lda = _mat(A, "A", V.dtype)
+    n, p = V.shape
+    n2, cols = A.shape
+    if n2 != n:
+        raise ValueError("A must have as many rows as V")
+    if r < 1 or cols % r:
+        raise ValueError("A must hold a whole number of r-column models")
+    models = cols // r
+    nup = _vec(nu, "nu", p)
+    lp = _vec(lam, "lambda", cols)
+    if prec is None:
+        prec = PREC_FP64 if V.dtype == torch.float64 else PREC_FP32
+    if out is None:
+        f = torch.empty(models, dtype=torch.float64, device=V.device)
+        g = torch.empty(cols, dtype=torch.float64, device=V.device)
+        G = colmajor(torch.empty(n, cols, dtype=V.dtype, device=V.device))
+    else:
+        f, g, G = out
+    Gp, ldg = _mat(G, "G_A", V.dtype)
+    st = lib().symtd_fg_multi(ctx.handle, _stream(stream), _dt(V), Vp, ldv, nup, n, p, Ap, lda, lp, int(r),
+                              int(models), int(d), float(alpha), int(prec), _vec(f, "f", models),
+                              _vec(g, "g_lambda", cols), Gp, ldg)
+    _check(ctx, st)
+    return f, g, G
+
+
+INIT_GAUSS, INIT_RRF = 0, 1
+ALPHA_COMPUTE, ALPHA_GIVEN, ALPHA_NONE = 0, 1, 2
+EXIT_NAMES = {0: "RUNNING", 1: "PGTOL", 2: "FTOL", 3: "MAX_ITERS", 4: "MAX_EVALS", 5: "LINESEARCH", 6: "NONFINITE"}
+
+
+def symtd_solve(ctx: Context, V, nu, d: int, r: int, *, prec: int | None = None, m: int = 5, pgtol: float = 1e-4,
+                ftol: float = 2.220446049250313e-09, max_iters: int = 10000, max_evals: int = 50000,
+                restarts: int = 1, seed: int = 0, init: int = INIT_RRF, alpha=None, A0=None,
+                check_every: int = 0, trace_len: int = 0, stream=None):
+    """Restarted L-BFGS solve on the device (symtd_solve).
+
+    alpha: None = compute ||X||^2 on the device, a positive number = use it,
+    0 = shifted objective.  A0 (optional): n x (restarts*r) column-major
+    device tensor of starts.  Returns a dict with the best model (A, lam as
+    device tensors) and the host figures of the solve.
+    """
+    import numpy as np
+    import torch
+    Vp, ldv = _mat(V, "V")
+    n, p = V.shape
+    nup = _vec(nu, "nu", p)
+    if prec is None:
+        prec = PREC_FP64 if V.dtype == torch.float64 else PREC_FP32
+    pb = Problem(_dt(V), Vp, ldv, nup, n, p, int(d), int(r))
+    o = SolveOpts()
+    _check(ctx, lib().symtd_solve_opts_default(ctypes.byref(o)))
+    o.prec, o.m, o.pgtol, o.ftol = int(prec), int(m), float(pgtol), float(ftol)
+    o.max_iters, o.max_evals, o.restarts, o.seed, o.init = int(max_iters), int(max_evals), int(restarts), int(seed), int(init)
+    if alpha is None:
+        o.alpha_mode = ALPHA_COMPUTE
+    elif float(alpha) > 0:
+        o.alpha_mode, o.alpha = ALPHA_GIVEN, float(alpha)
+    else:
+        o.alpha_mode = ALPHA_NONE
+    if A0 is not None:
+        A0p, lda0 = _mat(A0, "A0", V.dtype)
+        if A0.shape != (n, restarts * r) or lda0 != n:
+            raise ValueError("A0 must be an n x (restarts*r) column-major tensor with leading dimension n")
+        o.A0 = A0p
+    o.check_every = int(check_every)
+    A = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
+    lam = torch.empty(r, dtype=torch.float64, device=V.device)
+    Ap, lda = _mat(A, "A")
+    fr = np.zeros(restarts)
+    ir = np.zeros(restarts, dtype=np.int64)
+    er = np.zeros(restarts, dtype=np.int64)
+    xr = np.zeros(restarts, dtype=np.int32)
+    tr = np.zeros((restarts, max(trace_len, 1)))
+    res = SolveResult()
+    res.A, res.lda, res.lam = Ap, lda, lam.data_ptr()
+    res.f_restarts = fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    res.iters_restarts = ir.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    res.evals_restarts = er.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    res.exit_restarts = xr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    res.f_trace = tr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if trace_len > 0 else None
+    res.trace_len = int(trace_len)
+    _check(ctx, lib().symtd_solve(ctx.handle, _stream(stream), ctypes.byref(pb), ctypes.byref(o), ctypes.byref(res)))
+    return {"A": A, "lam": lam, "f": res.f, "alpha": res.alpha, "rel_err": res.rel_err, "iters": res.iters,
+            "evals": res.evals, "exit_reason": res.exit_reason, "best_restart": res.best_restart, "steps": res.steps,
+            "f_restarts": fr, "iters_restarts": ir, "evals_restarts": er, "exit_restarts": xr,
+            "f_trace": tr[:, :trace_len] if trace_len > 0 else None}
 
 
 def symtd_normX(ctx: Context, V, nu, d: int, out=None, stream=None):

@@ -496,25 +496,28 @@ __global__ __launch_bounds__(256) void k_gram_part(GramArgs<T> a) {
   __shared__ double sk[128][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int j0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
-  const int64_t i0 = (int64_t)blockIdx.z * 128;
+  const int grp = blockIdx.z % a.ng, split = blockIdx.z / a.ng;
+  const T* Ag = a.A + (int64_t)grp * a.r * a.lda;
+  const int64_t i0 = (int64_t)split * 128;
   for (int e = threadIdx.x; e < 128 * 16; e += 256) {
     const int ii = e & 127, cc = e >> 7;
     const int64_t i = i0 + ii;
     const int j = j0 + cc, k = k0 + cc;
-    sj[ii][cc] = (i < a.n && j < a.r) ? (double)a.A[(int64_t)j * a.lda + i] : 0.0;
-    sk[ii][cc] = (i < a.n && k < a.r) ? (double)a.A[(int64_t)k * a.lda + i] : 0.0;
+    sj[ii][cc] = (i < a.n && j < a.r) ? (double)Ag[(int64_t)j * a.lda + i] : 0.0;
+    sk[ii][cc] = (i < a.n && k < a.r) ? (double)Ag[(int64_t)k * a.lda + i] : 0.0;
   }
   __syncthreads();
   double acc = 0.0;
 #pragma unroll 16
   for (int ii = 0; ii < 128; ++ii) acc = fma(sj[ii][tx], sk[ii][ty], acc);
   const int j = j0 + tx, k = k0 + ty;
-  if (j < a.r && k < a.r) a.Bpart[(int64_t)blockIdx.z * a.r * a.r + (int64_t)k * a.r + j] = acc;
+  const int64_t rr = (int64_t)a.r * a.r;
+  if (j < a.r && k < a.r) a.Bpart[((int64_t)split * a.ng + grp) * rr + (int64_t)k * a.r + j] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_gram_fin(GramFinArgs a) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t rr = (int64_t)a.r * a.r;
+  const int64_t rr = a.rr;
   if (e >= rr) return;
   double b = 0.0;
   for (int s = 0; s < a.nsplit; ++s) b += a.Bpart[s * rr + e];
@@ -531,7 +534,11 @@ __global__ __launch_bounds__(256) void k_ymodel(YModelArgs<T> a) {
   __shared__ double sa[32][65];   // A D_lambda slice: [k][row]
   __shared__ double sc[32][17];   // C slice: [k][col]
   const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int j0 = blockIdx.y * 16;
+  const int grp = blockIdx.y / a.rt;
+  const int j0 = (blockIdx.y % a.rt) * 16;
+  const T* Ag = a.A + (int64_t)grp * a.r * a.lda;
+  const double* lg = a.lambda + (int64_t)grp * a.r;
+  const double* Cg = a.C + (int64_t)grp * a.r * a.r;
   const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;   // row, column quarter
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < a.r; k0 += 32) {
@@ -539,12 +546,12 @@ __global__ __launch_bounds__(256) void k_ymodel(YModelArgs<T> a) {
       const int ii = e & 63, kk = e >> 6;
       const int64_t i = i0 + ii;
       const int k = k0 + kk;
-      sa[kk][ii] = (i < a.n && k < a.r) ? (double)a.A[(int64_t)k * a.lda + i] * a.lambda[k] : 0.0;
+      sa[kk][ii] = (i < a.n && k < a.r) ? (double)Ag[(int64_t)k * a.lda + i] * lg[k] : 0.0;
     }
     for (int e = threadIdx.x; e < 32 * 16; e += 256) {
       const int cc = e & 15, kk = e >> 4;
       const int k = k0 + kk, j = j0 + cc;
-      sc[kk][cc] = (k < a.r && j < a.r) ? a.C[(int64_t)j * a.r + k] : 0.0;
+      sc[kk][cc] = (k < a.r && j < a.r) ? Cg[(int64_t)j * a.r + k] : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
@@ -560,7 +567,7 @@ __global__ __launch_bounds__(256) void k_ymodel(YModelArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = j0 + tc * 4 + q;
-      if (j < a.r) a.YM[(int64_t)j * a.n + i] = acc[q];
+      if (j < a.r) a.YM[((int64_t)grp * a.r + j) * a.n + i] = acc[q];
     }
   }
 }
@@ -582,13 +589,18 @@ __device__ __forceinline__ double block_sum_256(double v, double* sm) {
 
 __global__ __launch_bounds__(256) void k_final_s(FinalSArgs a) {
   __shared__ double sm[256];
-  const int j = blockIdx.x;
+  const int j = blockIdx.x;                 // column over all models
+  const int grp = j / a.r, jl = j - grp * a.r;
+  const int64_t rr = (int64_t)a.r * a.r;
+  const double* Bg = a.B + grp * rr;
+  const double* Cg = a.C + grp * rr;
+  const double* lg = a.lambda + (int64_t)grp * a.r;
   double w = 0.0;
   for (int64_t b = threadIdx.x; b < a.nwpart; b += 256) w += a.wpart[b * a.rp + j];
   w = block_sum_256(w, sm);
   double u = 0.0;
   for (int k = threadIdx.x; k < a.r; k += 256)
-    u += a.B[(int64_t)k * a.r + j] * a.C[(int64_t)k * a.r + j] * a.lambda[k];
+    u += Bg[(int64_t)k * a.r + jl] * Cg[(int64_t)k * a.r + jl] * lg[k];
   u = block_sum_256(u, sm);
   if (threadIdx.x == 0) {
     a.g_lambda[j] = -2.0 * (w - u);
@@ -596,12 +608,14 @@ __global__ __launch_bounds__(256) void k_final_s(FinalSArgs a) {
   }
 }
 
+// one block per model
 __global__ __launch_bounds__(256) void k_final_f(FinalSArgs a) {
   __shared__ double sm[256];
+  const int grp = blockIdx.x;
   double s = 0.0;
-  for (int j = threadIdx.x; j < a.r; j += 256) s += a.fpart[j];
+  for (int j = threadIdx.x; j < a.r; j += 256) s += a.fpart[(int64_t)grp * a.r + j];
   s = block_sum_256(s, sm);
-  if (threadIdx.x == 0) a.f[0] = a.alpha + s;
+  if (threadIdx.x == 0) a.f[grp] = a.alpha + s;
 }
 
 // ---------------------------------------------------------------------------
@@ -718,8 +732,8 @@ void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<double>& a) {
 void launch_final_s(dim3 grid, hipStream_t st, const FinalSArgs& a) {
   hipLaunchKernelGGL(k_final_s, grid, dim3(256), 0, st, a);
 }
-void launch_final_f(hipStream_t st, const FinalSArgs& a) {
-  hipLaunchKernelGGL(k_final_f, dim3(1), dim3(256), 0, st, a);
+void launch_final_f(dim3 grid, hipStream_t st, const FinalSArgs& a) {
+  hipLaunchKernelGGL(k_final_f, grid, dim3(256), 0, st, a);
 }
 
 }  // namespace symtd

@@ -75,22 +75,24 @@ struct PackAArgs {
 // k values per gemm1 chunk (one G1_RUN-byte run per column)
 template <typename T> constexpr int g1_chunk() { return G1_RUN / (int)sizeof(T); }
 
+// The model terms work on ng independent models of r columns each, stored
+// side by side (model m = columns m*r .. m*r + r - 1 of A, lambda, G_A).
 template <typename T>
 struct GramArgs {
-  const T* A; int64_t lda; int n; int r;
-  double* Bpart;      // [ceil(n/128)][r][r]
+  const T* A; int64_t lda; int n; int r; int ng;
+  double* Bpart;      // [ceil(n/128)][ng][r][r]
 };
 
 struct GramFinArgs {
-  const double* Bpart; int nsplit; int r; int d;
-  double* B; double* C;  // r x r, column-major
+  const double* Bpart; int nsplit; int64_t rr; int d;   // rr = ng * r * r
+  double* B; double* C;  // ng blocks of r x r, column-major
 };
 
 template <typename T>
 struct YModelArgs {
-  const T* A; int64_t lda; int n; int r;
+  const T* A; int64_t lda; int n; int r; int ng; int rt;   // rt = ceil(r / 16)
   const double* lambda; const double* C;
-  double* YM;         // n x r, leading dimension n
+  double* YM;         // n x (ng r), leading dimension n
 };
 
 template <typename T>
@@ -104,9 +106,9 @@ struct FinalGArgs {
 struct FinalSArgs {
   const double* wpart; int64_t nwpart; int64_t rp;
   const double* B; const double* C; const double* lambda;
-  int r; double alpha;
-  double* fpart;      // r per-column shares of f
-  double* f; double* g_lambda;
+  int r; int ng; double alpha;
+  double* fpart;      // ng r per-column shares of f
+  double* f; double* g_lambda;   // f: ng values
 };
 
 template <typename S>
@@ -134,7 +136,7 @@ void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<double>& a);
 void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<float>& a);
 void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<double>& a);
 void launch_final_s(dim3 grid, hipStream_t st, const FinalSArgs& a);
-void launch_final_f(hipStream_t st, const FinalSArgs& a);
+void launch_final_f(dim3 grid, hipStream_t st, const FinalSArgs& a);
 
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<float>& a);
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<double>& a);

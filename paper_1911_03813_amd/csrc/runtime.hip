@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "lbfgs.hpp"
 #include "runtime.hpp"
 
 using namespace symtd;
@@ -46,6 +47,23 @@ symtd_status symtd_ctx::reserve(size_t bytes) {
     return fail(SYMTD_ENOMEM, "hipMalloc(%zu bytes) for the workspace failed: %s", want, hipGetErrorString(e));
   }
   ws_bytes = want;
+  return SYMTD_OK;
+}
+
+symtd_status symtd_ctx::reserve_solver(size_t bytes) {
+  if (bytes <= sws_bytes) return SYMTD_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  if (sws) (void)hipFree(sws);
+  sws = nullptr;
+  sws_bytes = 0;
+  const size_t want = std::max(bytes, (size_t)1 << 20);
+  e = hipMalloc(&sws, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SYMTD_ENOMEM, "hipMalloc(%zu bytes) for the solver state failed: %s", want, hipGetErrorString(e));
+  }
+  sws_bytes = want;
   return SYMTD_OK;
 }
 
@@ -145,12 +163,20 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   return P;
 }
 
+}  // namespace
+
+namespace symtd {
+
 template <typename T>
 symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu,
-                    int64_t n, int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r,
+                    int64_t n, int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int ng,
                     int d, double alpha, double* f, double* g_lambda, T* G, int64_t ldg) {
   const bool f64 = sizeof(T) == 8;
-  const FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count, ctx->tune_g1_blocks, ctx->tune_g2_splits);
+  const int64_t r1 = r;            // columns of one model
+  r = r1 * ng;                     // columns of all models (the products see them all)
+  FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count, ctx->tune_g1_blocks, ctx->tune_g2_splits);
+  P.rr = (size_t)ng * r1 * r1;
+  P.bpart = (size_t)P.gsplit * P.rr;
   if (P.nblocks > ctx->nflags) return ctx->fail(SYMTD_EINVAL, "internal: %d blocks exceed the flag array", P.nblocks);
   symtd_status s = ctx->reserve(P.bytes(sizeof(T)));
   if (s != SYMTD_OK) return s;
@@ -175,14 +201,14 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   (void)hipEventRecord(ctx->ev_fork, st);
   (void)hipStreamWaitEvent(side, ctx->ev_fork, 0);
   {
-    GramArgs<T> ga{A, lda, (int)n, (int)r, Bpart};
-    const unsigned rt = (unsigned)((r + 15) / 16);
+    GramArgs<T> ga{A, lda, (int)n, (int)r1, ng, Bpart};
+    const unsigned rt = (unsigned)((r1 + 15) / 16);
     ctx->prof_begin(2, side);
-    launch_gram(dim3(rt, rt, (unsigned)P.gsplit), side, ga);
-    GramFinArgs gf{Bpart, P.gsplit, (int)r, d, B, C};
+    launch_gram(dim3(rt, rt, (unsigned)(P.gsplit * ng)), side, ga);
+    GramFinArgs gf{Bpart, P.gsplit, (int64_t)P.rr, d, B, C};
     launch_gram_fin(dim3((unsigned)((P.rr + 255) / 256)), side, gf);
-    YModelArgs<T> ya{A, lda, (int)n, (int)r, lambda, C, YM};
-    launch_ymodel(dim3((unsigned)((n + 63) / 64), rt), side, ya);
+    YModelArgs<T> ya{A, lda, (int)n, (int)r1, ng, (int)rt, lambda, C, YM};
+    launch_ymodel(dim3((unsigned)((n + 63) / 64), rt * (unsigned)ng), side, ya);
     ctx->prof_end(side);
     (void)hipEventRecord(ctx->ev_model, side);
   }
@@ -206,10 +232,10 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   (void)hipEventRecord(ctx->ev_g1, st);
   (void)hipStreamWaitEvent(side, ctx->ev_g1, 0);
   {
-    FinalSArgs as{wpart, (int64_t)G1_WAVES * P.nblocks, P.rp, B, C, lambda, (int)r, alpha, fpart, f, g_lambda};
+    FinalSArgs as{wpart, (int64_t)G1_WAVES * P.nblocks, P.rp, B, C, lambda, (int)r1, ng, alpha, fpart, f, g_lambda};
     ctx->prof_begin(4, side);
     launch_final_s(dim3((unsigned)r), side, as);
-    launch_final_f(side, as);
+    launch_final_f(dim3((unsigned)ng), side, as);
     ctx->prof_end(side);
     (void)hipEventRecord(ctx->ev_side, side);
   }
@@ -238,6 +264,44 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   return SYMTD_OK;
 }
 
+template symtd_status run_fg<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t,
+                                    int64_t, const float*, int64_t, const double*, int64_t, int, int, double,
+                                    double*, double*, float*, int64_t);
+template symtd_status run_fg<double>(symtd_ctx*, hipStream_t, const double*, int64_t, const double*, int64_t,
+                                     int64_t, const double*, int64_t, const double*, int64_t, int, int, double,
+                                     double*, double*, double*, int64_t);
+
+template <typename T>
+symtd_status run_rrf(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, int64_t n, int64_t p, int64_t r,
+                     int restarts, uint64_t seed, const LbLane<T>* lanes_dev) {
+  const bool f64 = sizeof(T) == 8;
+  const FgPlan P = plan_fg(n, p, r * restarts, f64, ctx->cu_count, 0, ctx->tune_g2_splits);
+  symtd_status s = ctx->reserve(P.bytes(sizeof(T)));
+  if (s != SYMTD_OK) return s;
+  Carve cv(ctx->ws);
+  T* Wp = cv.take<T>(P.wp);
+  T* Ypart = cv.take<T>(P.ypart);
+  launch_omega_packed<T>(dim3((unsigned)((P.wp + 255) / 256)), st, Wp, p, (int)r, restarts, P.nt_tot, P.nblk, seed);
+  const size_t vq = 16 / sizeof(T);
+  const bool vecV = aligned_to<T>(V, 16) && (ldv % vq) == 0;
+  for (int t0 = 0; t0 < P.nt_tot; t0 += P.nt2) {
+    const int nt = std::min(P.nt2, P.nt_tot - t0);
+    G2Args<T> a2{V, ldv, (int)n, (int)p, Wp, P.nt_tot, P.rp, 16 * t0, P.nblk, P.blk_per_split,
+                 P.nsplit, P.rowblocks, Ypart, P.npad};
+    const unsigned blocks = (unsigned)(P.rowblocks * 8 * ((P.nsplit + 7) / 8));
+    launch_gemm2(nt, vecV && (n % 4) == 0, dim3(blocks), st, a2);
+  }
+  launch_rrf_finish<T>(restarts, (int)r, st, lanes_dev, Ypart, P.npad, P.rp, P.nsplit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return ctx->hip_fail(e, "kernel launch (rrf)");
+  return SYMTD_OK;
+}
+
+template symtd_status run_rrf<float>(symtd_ctx*, hipStream_t, const float*, int64_t, int64_t, int64_t, int64_t, int,
+                                     uint64_t, const LbLane<float>*);
+template symtd_status run_rrf<double>(symtd_ctx*, hipStream_t, const double*, int64_t, int64_t, int64_t, int64_t,
+                                      int, uint64_t, const LbLane<double>*);
+
 template <typename S>
 symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, const double* nu,
                        int64_t n, int64_t p, int d, double* alpha) {
@@ -262,7 +326,12 @@ symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, 
   return SYMTD_OK;
 }
 
-}  // namespace
+template symtd_status run_normx<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t,
+                                       int64_t, int, double*);
+template symtd_status run_normx<double>(symtd_ctx*, hipStream_t, const double*, int64_t, const double*, int64_t,
+                                        int64_t, int, double*);
+
+}  // namespace symtd
 
 // ---------------------------------------------------------------------------
 // argument checks shared by the entry points
@@ -344,6 +413,8 @@ void symtd_destroy(symtd_ctx* ctx) {
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->flags) (void)hipFree(ctx->flags);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->sws) (void)hipFree(ctx->sws);
+  if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
   delete ctx;
 }
 
@@ -356,11 +427,20 @@ symtd_status symtd_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* 
                       const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
                       const double* lambda, int64_t r, int d, double alpha, symtd_prec prec,
                       double* f, double* g_lambda, void* G_A, int64_t ldg) {
+  return symtd_fg_multi(ctx, stream, dt, V, ldv, nu, n, p, A, lda, lambda, r, 1, d, alpha, prec, f, g_lambda,
+                        G_A, ldg);
+}
+
+symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
+                            const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
+                            const double* lambda, int64_t r, int64_t models, int d, double alpha, symtd_prec prec,
+                            double* f, double* g_lambda, void* G_A, int64_t ldg) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
   symtd_status s = ctx->check_common(dt, V, ldv, nu, n, p, d);
   if (s != SYMTD_OK) return s;
-  if (r < 1 || r > 0x7fffffffLL) return ctx->fail(SYMTD_EINVAL, "rank r=%lld must be >= 1", (long long)r);
+  if (r < 1 || models < 1 || r * models > 0x7fffffffLL)
+    return ctx->fail(SYMTD_EINVAL, "rank r=%lld and models=%lld must be >= 1", (long long)r, (long long)models);
   if (lda < n || ldg < n) return ctx->fail(SYMTD_EINVAL, "lda=%lld and ldg=%lld must be >= n=%lld",
                                            (long long)lda, (long long)ldg, (long long)n);
   if (!A || !lambda || !f || !g_lambda || !G_A) return ctx->fail(SYMTD_EINVAL, "null A, lambda, f, g_lambda or G_A");
@@ -373,10 +453,10 @@ symtd_status symtd_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* 
   if ((s = ctx->set_device()) != SYMTD_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if (dt == SYMTD_F64)
-    return run_fg<double>(ctx, st, (const double*)V, ldv, nu, n, p, (const double*)A, lda, lambda, r, d, alpha, f,
-                          g_lambda, (double*)G_A, ldg);
-  return run_fg<float>(ctx, st, (const float*)V, ldv, nu, n, p, (const float*)A, lda, lambda, r, d, alpha, f,
-                       g_lambda, (float*)G_A, ldg);
+    return run_fg<double>(ctx, st, (const double*)V, ldv, nu, n, p, (const double*)A, lda, lambda, r, (int)models, d,
+                          alpha, f, g_lambda, (double*)G_A, ldg);
+  return run_fg<float>(ctx, st, (const float*)V, ldv, nu, n, p, (const float*)A, lda, lambda, r, (int)models, d,
+                       alpha, f, g_lambda, (float*)G_A, ldg);
 }
 
 symtd_status symtd_normX(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,

@@ -12,8 +12,11 @@ struct symtd_ctx {
   int device = 0;
   int cu_count = 256;
   std::string err;
-  void* ws = nullptr;   // device workspace, grown on demand
+  void* ws = nullptr;   // device workspace of the evaluation, grown on demand
   size_t ws_bytes = 0;
+  void* sws = nullptr;  // device workspace of the solver state, grown on demand
+  size_t sws_bytes = 0;
+  int* host_flag = nullptr;   // pinned host word for polling the solver's stop count
   // side stream for the model terms, and the events of the fork/join
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_model = nullptr, ev_g1 = nullptr, ev_side = nullptr;
@@ -33,9 +36,35 @@ struct symtd_ctx {
   symtd_status fail(symtd_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
   symtd_status hip_fail(hipError_t e, const char* what);
   symtd_status reserve(size_t bytes);
+  symtd_status reserve_solver(size_t bytes);
   symtd_status set_device();
   symtd_status check_common(symtd_dtype dt, const void* V, int64_t ldv, const double* nu,
                             int64_t n, int64_t p, int d);
   void prof_begin(int which, hipStream_t st);
   void prof_end(hipStream_t st);
 };
+
+namespace symtd {
+
+// Algorithm 2 for `ng` models of r columns side by side (model m = columns
+// m r .. m r + r - 1 of A, lambda, g_lambda, G_A; f holds ng values).
+// Arguments are checked by the caller.
+template <typename T>
+symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu,
+                    int64_t n, int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int ng,
+                    int d, double alpha, double* f, double* g_lambda, T* G, int64_t ldg);
+
+// Randomized range finder starts of `restarts` lanes (restart k = columns
+// k r .. k r + r - 1 of V Omega), normalised, written into each lane's x and
+// trial point.  Uses the evaluation workspace.
+template <typename T> struct LbLane;
+template <typename T>
+symtd_status run_rrf(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, int64_t n, int64_t p, int64_t r,
+                     int restarts, uint64_t seed, const LbLane<T>* lanes_dev);
+
+// alpha = ||X||^2 into one device fp64 value.  Arguments checked by the caller.
+template <typename S>
+symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, const double* nu,
+                       int64_t n, int64_t p, int d, double* alpha);
+
+}  // namespace symtd

@@ -54,3 +54,43 @@ def test_null_context_rejected():
 def test_profile_names():
     names = S.profile_names()
     assert names[:2] == ["gemm1", "gemm2"]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors of the solve structs have the C header's sizes and offsets
+    import ctypes
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    pass
+    checks = {
+        "symtd_problem": (S.Problem, ["dt", "V", "ldv", "nu", "n", "p", "d", "r"]),
+        "symtd_solve_opts": (S.SolveOpts, ["prec", "m", "pgtol", "ftol", "max_iters", "max_evals", "restarts",
+                                           "seed", "init", "alpha_mode", "alpha", "A0", "check_every"]),
+        "symtd_solve_result": (S.SolveResult, ["A", "lda", "lambda", "f_restarts", "iters_restarts",
+                                               "evals_restarts", "exit_restarts", "f_trace", "trace_len", "f",
+                                               "alpha", "rel_err", "iters", "evals", "exit_reason",
+                                               "best_restart", "steps"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "symtd.h"', "int main(void) {"]
+    for cname, (_, fields) in checks.items():
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        for fld in fields:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {fld}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = []
+    for cname, (cls, fields) in checks.items():
+        want.append(ctypes.sizeof(cls))
+        names = [f[0] for f in cls._fields_]
+        for fld in fields:
+            fld_py = "lam" if fld == "lambda" else fld
+            assert fld_py in names, (cname, fld)
+            want.append(getattr(cls, fld_py).offset)
+    assert got == want

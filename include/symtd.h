@@ -222,6 +222,40 @@ symtd_status symtd_solve_opts_default(symtd_solve_opts* opts);
 symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb,
                          const symtd_solve_opts* opts, symtd_solve_result* out);
 
+/* ------------------------------------------------------------------------
+ * Batched forms: many independent problems of uneven shape at once.
+ *
+ * Every problem is one instance of the grouped kernels: each evaluation step
+ * runs four launches for all instances (first product with its epilogue, fp64
+ * model terms, split second product, G_A assembly), driven by tables of work
+ * items (instance, tile, column group ...), so the device is filled by many
+ * small products.  An instance's tiles, splits and summation orders depend
+ * only on its own shape: its results are the same bits whatever else is in
+ * the batch.  (These kernels differ from the single-instance ones, so the
+ * batched and single forms agree to the stated tolerances, not bitwise.)
+ * ------------------------------------------------------------------------ */
+typedef struct symtd_fg_item {
+  const void* V; int64_t ldv; const double* nu; int64_t n, p; int d;
+  const void* A; int64_t lda; const double* lambda; int64_t r; int64_t models;
+  double alpha;
+  double* f;                /* models values */
+  double* g_lambda;         /* models * r values */
+  void* G_A; int64_t ldg;   /* n x (models r); rows n .. ldg-1 are not written */
+} symtd_fg_item;
+
+/* symtd_fg_multi for every item (all items share dt and prec).  Device
+ * pointers as in symtd_fg; the call synchronises `stream` before returning. */
+symtd_status symtd_fg_batched(symtd_ctx* ctx, void* stream, symtd_dtype dt, symtd_prec prec,
+                              int64_t count, const symtd_fg_item* items);
+
+/* symtd_solve for every problem (problem i with options opts[i], results in
+ * outs[i]; all problems share dt), all advanced together on the grouped
+ * engine: each problem's restarts are lanes of the device L-BFGS, one
+ * evaluation step evaluates every live lane, finished problems leave the
+ * step tables.  The starts are drawn as in symtd_solve.  Synchronous. */
+symtd_status symtd_solve_batched(symtd_ctx* ctx, void* stream, int64_t count, const symtd_problem* pbs,
+                                 const symtd_solve_opts* opts, symtd_solve_result* outs);
+
 /*
  * Work-split tuning of the evaluation kernels (used by the autotuner and by
  * tests that force particular splits). Keys:
@@ -233,10 +267,13 @@ symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb,
  *   SYMTD_TUNE_SERIAL     1 = run the small model-term kernels (A'A, A D C) on
  *                         the caller's stream before the products; 0 (default)
  *                         = on the context's side stream, overlapped with them
+ *   SYMTD_TUNE_GRAPH      grouped engine (batched solve, server): 1 (default)
+ *                         = capture one evaluation step as a hipGraph and
+ *                         replay it; 0 = launch the step's kernels eagerly
  * Values must be >= 0; results do not depend on them beyond rounding order.
  */
 typedef enum symtd_tune_key {
-  SYMTD_TUNE_G1_BLOCKS = 0, SYMTD_TUNE_G2_SPLITS = 1, SYMTD_TUNE_SERIAL = 2
+  SYMTD_TUNE_G1_BLOCKS = 0, SYMTD_TUNE_G2_SPLITS = 1, SYMTD_TUNE_SERIAL = 2, SYMTD_TUNE_GRAPH = 3
 } symtd_tune_key;
 symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value);
 

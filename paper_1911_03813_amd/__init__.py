@@ -50,6 +50,15 @@ class SolveOpts(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("A0", ctypes.c_void_p), ("check_every", ctypes.c_int)]
 
 
+class FgItem(ctypes.Structure):
+    """symtd_fg_item"""
+    _fields_ = [("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("nu", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("p", ctypes.c_int64), ("d", ctypes.c_int), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("lam", ctypes.c_void_p), ("r", ctypes.c_int64), ("models", ctypes.c_int64),
+                ("alpha", ctypes.c_double), ("f", ctypes.c_void_p), ("g_lambda", ctypes.c_void_p),
+                ("G_A", ctypes.c_void_p), ("ldg", ctypes.c_int64)]
+
+
 class SolveResult(ctypes.Structure):
     """symtd_solve_result"""
     _fields_ = [("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("lam", ctypes.c_void_p),
@@ -79,6 +88,9 @@ SIGNATURES = {
     "symtd_set_tuning": (_int, [_vp, _int, _i64]),
     "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
     "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
+    "symtd_fg_batched": (_int, [_vp, _vp, _int, _int, _i64, _c.POINTER(FgItem)]),
+    "symtd_solve_batched": (_int, [_vp, _vp, _i64, _c.POINTER(Problem), _c.POINTER(SolveOpts),
+                                   _c.POINTER(SolveResult)]),
     "symtd_profile_enable": (_int, [_vp, _int]),
     "symtd_profile_reset": (_int, [_vp]),
     "symtd_profile_read": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
@@ -103,7 +115,7 @@ def lib():
 
 def _check(ctx, status: int):
     if status != SYMTD_OK:
-        msg = lib().symtd_last_error(ctx._h if ctx is not None else None)
+        msg = lib().symtd_last_error(ctx._h if ctx is not None else None) if ctx is not None else b""
         raise SymtdError(status, msg.decode() if msg else "")
 
 
@@ -252,6 +264,68 @@ ALPHA_COMPUTE, ALPHA_GIVEN, ALPHA_NONE = 0, 1, 2
 EXIT_NAMES = {0: "RUNNING", 1: "PGTOL", 2: "FTOL", 3: "MAX_ITERS", 4: "MAX_EVALS", 5: "LINESEARCH", 6: "NONFINITE"}
 
 
+class _SolveCall:
+    """Marshalled arguments and host result buffers of one solve request."""
+
+    def __init__(self, V, nu, d, r, prec=None, m=5, pgtol=1e-4, ftol=2.220446049250313e-09, max_iters=10000,
+                 max_evals=50000, restarts=1, seed=0, init=None, alpha=None, A0=None, check_every=0,
+                 trace_len=0):
+        import numpy as np
+        import torch
+        Vp, ldv = _mat(V, "V")
+        n, p = V.shape
+        nup = _vec(nu, "nu", p)
+        if prec is None:
+            prec = PREC_FP64 if V.dtype == torch.float64 else PREC_FP32
+        self.pb = Problem(_dt(V), Vp, ldv, nup, n, p, int(d), int(r))
+        o = SolveOpts()
+        _check(None, lib().symtd_solve_opts_default(ctypes.byref(o)))
+        o.prec, o.m, o.pgtol, o.ftol = int(prec), int(m), float(pgtol), float(ftol)
+        o.max_iters, o.max_evals, o.restarts, o.seed = int(max_iters), int(max_evals), int(restarts), int(seed)
+        o.init = INIT_RRF if init is None else int(init)
+        if alpha is None:
+            o.alpha_mode = ALPHA_COMPUTE
+        elif float(alpha) > 0:
+            o.alpha_mode, o.alpha = ALPHA_GIVEN, float(alpha)
+        else:
+            o.alpha_mode = ALPHA_NONE
+        self.keep = [V, nu]
+        if A0 is not None:
+            A0p, lda0 = _mat(A0, "A0", V.dtype)
+            if tuple(A0.shape) != (n, restarts * r) or lda0 != n:
+                raise ValueError("A0 must be an n x (restarts*r) column-major tensor with leading dimension n")
+            o.A0 = A0p
+            self.keep.append(A0)
+        o.check_every = int(check_every)
+        self.opts = o
+        self.A = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
+        self.lam = torch.empty(r, dtype=torch.float64, device=V.device)
+        Ap, lda = _mat(self.A, "A")
+        self.fr = np.zeros(restarts)
+        self.ir = np.zeros(restarts, dtype=np.int64)
+        self.er = np.zeros(restarts, dtype=np.int64)
+        self.xr = np.zeros(restarts, dtype=np.int32)
+        self.trace_len = int(trace_len)
+        self.tr = np.zeros((restarts, max(trace_len, 1)))
+        res = SolveResult()
+        res.A, res.lda, res.lam = Ap, lda, self.lam.data_ptr()
+        res.f_restarts = self.fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        res.iters_restarts = self.ir.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        res.evals_restarts = self.er.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        res.exit_restarts = self.xr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        res.f_trace = self.tr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if trace_len > 0 else None
+        res.trace_len = self.trace_len
+        self.res = res
+
+    def result(self, res=None):
+        res = self.res if res is None else res
+        return {"A": self.A, "lam": self.lam, "f": res.f, "alpha": res.alpha, "rel_err": res.rel_err,
+                "iters": res.iters, "evals": res.evals, "exit_reason": res.exit_reason,
+                "best_restart": res.best_restart, "steps": res.steps, "f_restarts": self.fr,
+                "iters_restarts": self.ir, "evals_restarts": self.er, "exit_restarts": self.xr,
+                "f_trace": self.tr[:, :self.trace_len] if self.trace_len > 0 else None}
+
+
 def symtd_solve(ctx: Context, V, nu, d: int, r: int, *, prec: int | None = None, m: int = 5, pgtol: float = 1e-4,
                 ftol: float = 2.220446049250313e-09, max_iters: int = 10000, max_evals: int = 50000,
                 restarts: int = 1, seed: int = 0, init: int = INIT_RRF, alpha=None, A0=None,
@@ -263,51 +337,53 @@ def symtd_solve(ctx: Context, V, nu, d: int, r: int, *, prec: int | None = None,
     device tensor of starts.  Returns a dict with the best model (A, lam as
     device tensors) and the host figures of the solve.
     """
-    import numpy as np
+    call = _SolveCall(V, nu, d, r, prec, m, pgtol, ftol, max_iters, max_evals, restarts, seed, init, alpha, A0,
+                      check_every, trace_len)
+    _check(ctx, lib().symtd_solve(ctx.handle, _stream(stream), ctypes.byref(call.pb), ctypes.byref(call.opts),
+                                  ctypes.byref(call.res)))
+    return call.result()
+
+
+def symtd_solve_batched(ctx: Context, problems, stream=None):
+    """symtd_solve for every problem (dicts with V, nu, d, r and symtd_solve's
+    keyword options), all on the grouped engine.  Returns one result dict per
+    problem."""
+    calls = [_SolveCall(**pr) for pr in problems]
+    k = len(calls)
+    pbs = (Problem * k)(*[c.pb for c in calls])
+    opts = (SolveOpts * k)(*[c.opts for c in calls])
+    outs = (SolveResult * k)(*[c.res for c in calls])
+    _check(ctx, lib().symtd_solve_batched(ctx.handle, _stream(stream), k, pbs, opts, outs))
+    return [c.result(outs[i]) for i, c in enumerate(calls)]
+
+
+def symtd_fg_batched(ctx: Context, items, stream=None):
+    """symtd_fg_multi for every item (dicts with V, nu, A, lam, r, d and
+    optional alpha).  Returns [(f, g_lambda, G_A)] per item."""
     import torch
-    Vp, ldv = _mat(V, "V")
-    n, p = V.shape
-    nup = _vec(nu, "nu", p)
-    if prec is None:
-        prec = PREC_FP64 if V.dtype == torch.float64 else PREC_FP32
-    pb = Problem(_dt(V), Vp, ldv, nup, n, p, int(d), int(r))
-    o = SolveOpts()
-    _check(ctx, lib().symtd_solve_opts_default(ctypes.byref(o)))
-    o.prec, o.m, o.pgtol, o.ftol = int(prec), int(m), float(pgtol), float(ftol)
-    o.max_iters, o.max_evals, o.restarts, o.seed, o.init = int(max_iters), int(max_evals), int(restarts), int(seed), int(init)
-    if alpha is None:
-        o.alpha_mode = ALPHA_COMPUTE
-    elif float(alpha) > 0:
-        o.alpha_mode, o.alpha = ALPHA_GIVEN, float(alpha)
-    else:
-        o.alpha_mode = ALPHA_NONE
-    if A0 is not None:
-        A0p, lda0 = _mat(A0, "A0", V.dtype)
-        if A0.shape != (n, restarts * r) or lda0 != n:
-            raise ValueError("A0 must be an n x (restarts*r) column-major tensor with leading dimension n")
-        o.A0 = A0p
-    o.check_every = int(check_every)
-    A = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
-    lam = torch.empty(r, dtype=torch.float64, device=V.device)
-    Ap, lda = _mat(A, "A")
-    fr = np.zeros(restarts)
-    ir = np.zeros(restarts, dtype=np.int64)
-    er = np.zeros(restarts, dtype=np.int64)
-    xr = np.zeros(restarts, dtype=np.int32)
-    tr = np.zeros((restarts, max(trace_len, 1)))
-    res = SolveResult()
-    res.A, res.lda, res.lam = Ap, lda, lam.data_ptr()
-    res.f_restarts = fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    res.iters_restarts = ir.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-    res.evals_restarts = er.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-    res.exit_restarts = xr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
-    res.f_trace = tr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if trace_len > 0 else None
-    res.trace_len = int(trace_len)
-    _check(ctx, lib().symtd_solve(ctx.handle, _stream(stream), ctypes.byref(pb), ctypes.byref(o), ctypes.byref(res)))
-    return {"A": A, "lam": lam, "f": res.f, "alpha": res.alpha, "rel_err": res.rel_err, "iters": res.iters,
-            "evals": res.evals, "exit_reason": res.exit_reason, "best_restart": res.best_restart, "steps": res.steps,
-            "f_restarts": fr, "iters_restarts": ir, "evals_restarts": er, "exit_restarts": xr,
-            "f_trace": tr[:, :trace_len] if trace_len > 0 else None}
+    arr = (FgItem * len(items))()
+    outs = []
+    dt = None
+    for i, it in enumerate(items):
+        V, nu, A, lam, r, d = it["V"], it["nu"], it["A"], it["lam"], int(it["r"]), int(it["d"])
+        Vp, ldv = _mat(V, "V")
+        Ap, lda = _mat(A, "A", V.dtype)
+        n, p = V.shape
+        cols = A.shape[1]
+        if A.shape[0] != n or cols % r:
+            raise ValueError("A must be n x (models r)")
+        models = cols // r
+        f = torch.empty(models, dtype=torch.float64, device=V.device)
+        g = torch.empty(cols, dtype=torch.float64, device=V.device)
+        G = colmajor(torch.empty(n, cols, dtype=V.dtype, device=V.device))
+        Gp, ldg = _mat(G, "G_A")
+        arr[i] = FgItem(Vp, ldv, _vec(nu, "nu", p), n, p, d, Ap, lda, _vec(lam, "lambda", cols), r, models,
+                        float(it.get("alpha", 0.0)), f.data_ptr(), g.data_ptr(), Gp, ldg)
+        outs.append((f, g, G))
+        dt = _dt(V) if dt is None else dt
+    prec = PREC_FP64 if dt == F64 else PREC_FP32
+    _check(ctx, lib().symtd_fg_batched(ctx.handle, _stream(stream), dt, prec, len(items), arr))
+    return outs
 
 
 def symtd_normX(ctx: Context, V, nu, d: int, out=None, stream=None):
@@ -322,7 +398,7 @@ def symtd_normX(ctx: Context, V, nu, d: int, out=None, stream=None):
     return a
 
 
-TUNE_G1_BLOCKS, TUNE_G2_SPLITS, TUNE_SERIAL = 0, 1, 2
+TUNE_G1_BLOCKS, TUNE_G2_SPLITS, TUNE_SERIAL, TUNE_GRAPH = 0, 1, 2, 3
 
 
 def symtd_set_tuning(ctx: Context, key: int, value: int):

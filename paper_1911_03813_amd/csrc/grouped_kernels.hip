@@ -1,0 +1,363 @@
+// Grouped evaluation kernels (Algorithm 2 over many instances): see grouped.hpp.
+//
+// The products use the same MFMA operand conventions as the single-instance
+// kernels (kcommon.hpp): in ggemm1 a lane supplies observation l = 16 b + c
+// of its wave's 16-observation block as the A operand and factor column
+// 16 t + c as the B operand, each as 4 consecutive covariates read with one
+// vector load; the accumulators come out as Z[16 b + row(g, v)][16 t + c],
+// which is the packed order of W.  In ggemm2 a lane supplies 4 consecutive
+// rows of V (one per M subtile) and the packed W quad of its observations.
+// Instances are small (their data sits in L2), so both products read their
+// operands straight from memory; many items per step fill the chip.
+#include <type_traits>
+
+#include "grouped.hpp"
+#include "kcommon.hpp"
+#include "philox.hpp"
+
+namespace symtd {
+
+namespace {
+
+template <typename T, bool VEC>
+__device__ __forceinline__ void quad_at(Quad<T>& q, const T* col, int64_t i, int64_t n) {
+  if (VEC && i + 3 < n) vload4(q, col + i);
+  else load_tail(q, col, i, n);
+}
+
+// ---------------------------------------------------------------------------
+// ggemm1 body for NT column subtiles
+// ---------------------------------------------------------------------------
+template <typename T, int NT, bool VEC>
+__device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[GG_NT_F32 * 16]) {
+  using acc_t = typename Mfma<T>::acc_t;
+  constexpr int NTM = std::is_same<T, float>::value ? GG_NT_F32 : GG_NT_F64;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t n = I.n, p = I.p;
+  const int col0 = cg * NTM * 16;
+  const int dm1 = I.d - 1;
+  // factor columns of this lane (one per subtile); columns past cols read as zero
+  const T* acol[NT];
+  bool aok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = col0 + 16 * t + c;
+    aok[t] = col < I.cols;
+    acol[t] = I.A + (int64_t)(aok[t] ? col : 0) * I.lda;
+  }
+  double wsum[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) wsum[t] = 0.0;
+  const int64_t nblk = (p + 15) / 16;
+  for (int q = 0; q < GG1_TILE / 64; ++q) {
+    const int64_t b = (int64_t)tile * (GG1_TILE / 16) + 4 * q + wave;
+    if (b >= nblk) break;
+    const int64_t l = 16 * b + c;
+    const T* vcol = I.V + (l < p ? l : p - 1) * I.ldv;
+    acc_t acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    // the trip count is the same for every lane (MFMA is a whole-wave
+    // operation); covariates at or past n read as zero
+#pragma unroll 2
+    for (int64_t k0 = 0; k0 < n; k0 += 16) {
+      const int64_t k = k0 + 4 * g;
+      Quad<T> v;
+      quad_at<T, VEC>(v, vcol, k, n);
+      Quad<T> a[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        quad_at<T, VEC>(a[t], acol[t], k, n);
+        if (!aok[t]) zero4(a[t]);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::mac(v.e[s], a[t].e[s], acc[t]);
+    }
+    // epilogue: acc[t][v] = z at l = 16 b + row(g, v), column col0 + 16 t + c
+    double nl[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t lv = 16 * b + Mfma<T>::row(g, v);
+      nl[v] = lv < p ? I.nu[lv] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      Quad<T> wq;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double z = (double)acc[t][v];
+        const double wv = nl[v] * ipow(z, dm1);
+        wq.e[v] = (T)wv;
+        wsum[t] += wv * z;
+      }
+      vstore4(I.Wp + ((b * I.nt + cg * NTM + t) * 64 + lane) * 4, wq);
+    }
+  }
+  // column sums of nu z^d over this tile: lane groups, then waves (fixed order)
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    double s = wsum[t];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (g == 0) red[wave][16 * t + c] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NT * 16; e += 256) {
+    const int col = col0 + e;
+    if (col < I.cols)
+      I.wpart[(int64_t)tile * I.cols + col] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ggemm2 body for NT column subtiles: one wave, 64 rows
+// ---------------------------------------------------------------------------
+template <typename T, int NT, bool VEC>
+__device__ void ggemm2_body(const GInst<T>& I, int rb, int split, int cg) {
+  using acc_t = typename Mfma<T>::acc_t;
+  constexpr int NTM = std::is_same<T, float>::value ? GG_NT_F32 : GG_NT_F64;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t n = I.n, p = I.p;
+  const int64_t ibase = (int64_t)rb * 64;
+  const int64_t il = ibase + 4 * c;
+  const int64_t nblk = (p + 15) / 16;
+  const int64_t b0 = (int64_t)split * GG2_SPLIT_BLK;
+  const int64_t b1 = min(nblk, b0 + GG2_SPLIT_BLK);
+  acc_t acc[4][NT];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
+  for (int64_t b = b0; b < b1; ++b) {
+    Quad<T> w[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) vload4(w[t], I.Wp + ((b * I.nt + cg * NTM + t) * 64 + lane) * 4);
+    Quad<T> v[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int64_t l = 16 * b + Mfma<T>::row(g, s);
+      l = l < p ? l : p - 1;            // rows of W past p are zero
+      const T* col = I.V + l * I.ldv;
+      if (VEC && il + 3 < n) vload4(v[s], col + il);
+      else load_tail(v[s], col, il, n);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(v[s].e[m], w[t].e[s], acc[m][t]);
+  }
+  // acc[m][t][v] = Y[ibase + 4 row(g, v) + m][col0 + 16 t + c]
+  const int64_t rp = (int64_t)I.nt * 16;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    T* col = I.Ypart + ((int64_t)split * rp + cg * NTM * 16 + 16 * t + c) * I.ldy;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Quad<T> q;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) q.e[m] = acc[m][t][v];
+      vstore4(col + ibase + 4 * Mfma<T>::row(g, v), q);
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_ggemm1(const GInst<T>* insts, const GItem* items) {
+  __shared__ double red[4][GG_NT_F32 * 16];
+  const GItem it = items[blockIdx.x];
+  const GInst<T> I = insts[it.inst];
+  constexpr int NTM = std::is_same<T, float>::value ? GG_NT_F32 : GG_NT_F64;
+  const int ntg = min(NTM, I.nt - it.b * NTM);
+  switch (ntg) {
+    case 1: ggemm1_body<T, 1, VEC>(I, it.a, it.b, red); break;
+    case 2: ggemm1_body<T, 2, VEC>(I, it.a, it.b, red); break;
+    case 3: ggemm1_body<T, 3, VEC>(I, it.a, it.b, red); break;
+    case 4: ggemm1_body<T, 4, VEC>(I, it.a, it.b, red); break;
+    default:
+      if constexpr (NTM > 4) {
+        switch (ntg) {
+          case 5: ggemm1_body<T, 5, VEC>(I, it.a, it.b, red); break;
+          case 6: ggemm1_body<T, 6, VEC>(I, it.a, it.b, red); break;
+          case 7: ggemm1_body<T, 7, VEC>(I, it.a, it.b, red); break;
+          case 8: ggemm1_body<T, 8, VEC>(I, it.a, it.b, red); break;
+          default: break;
+        }
+      }
+  }
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(64) void k_ggemm2(const GInst<T>* insts, const GItem* items) {
+  const GItem it = items[blockIdx.x];
+  const GInst<T> I = insts[it.inst];
+  constexpr int NTM = std::is_same<T, float>::value ? GG_NT_F32 : GG_NT_F64;
+  const int ntg = min(NTM, I.nt - it.c * NTM);
+  switch (ntg) {
+    case 1: ggemm2_body<T, 1, VEC>(I, it.a, it.b, it.c); break;
+    case 2: ggemm2_body<T, 2, VEC>(I, it.a, it.b, it.c); break;
+    case 3: ggemm2_body<T, 3, VEC>(I, it.a, it.b, it.c); break;
+    case 4: ggemm2_body<T, 4, VEC>(I, it.a, it.b, it.c); break;
+    default:
+      if constexpr (NTM > 4) {
+        switch (ntg) {
+          case 5: ggemm2_body<T, 5, VEC>(I, it.a, it.b, it.c); break;
+          case 6: ggemm2_body<T, 6, VEC>(I, it.a, it.b, it.c); break;
+          case 7: ggemm2_body<T, 7, VEC>(I, it.a, it.b, it.c); break;
+          case 8: ggemm2_body<T, 8, VEC>(I, it.a, it.b, it.c); break;
+          default: break;
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gmodel: one block per (instance, model): B, C, u, w, f, g_lambda, Y_M (fp64)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GItem* items) {
+  const GItem it = items[blockIdx.x];
+  const GInst<T> I = insts[it.inst];
+  const int k = it.a;                       // model
+  const int r = I.r, n = I.n;
+  const int64_t rr = (int64_t)r * r;
+  const T* A = I.A + (int64_t)k * r * I.lda;
+  const double* lam = I.lam + (int64_t)k * r;
+  double* B = I.B + k * rr;
+  double* C = I.C + k * rr;
+  // B = A'A (upper pairs, mirrored), C = B^{d-1}
+  for (int e = threadIdx.x; e < r * r; e += 256) {
+    const int j = e % r, l = e / r;
+    if (j > l) continue;
+    const T* aj = A + (int64_t)j * I.lda;
+    const T* al = A + (int64_t)l * I.lda;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s = fma((double)aj[i], (double)al[i], s);
+    const double cv = ipow(s, I.d - 1);
+    B[(int64_t)l * r + j] = s; B[(int64_t)j * r + l] = s;
+    C[(int64_t)l * r + j] = cv; C[(int64_t)j * r + l] = cv;
+  }
+  __syncthreads();
+  // u, w, g_lambda and f: thread t handles columns t, t + 256, ... and its
+  // share of f; the shares are then summed in thread order
+  __shared__ double fs[256];
+  double fsh = 0.0;
+  for (int j = threadIdx.x; j < r; j += 256) {
+    double u = 0.0;
+    for (int l = 0; l < r; ++l) u += B[(int64_t)l * r + j] * C[(int64_t)l * r + j] * lam[l];
+    double w = 0.0;
+    const int col = k * r + j;
+    for (int t = 0; t < I.ntile; ++t) w += I.wpart[(int64_t)t * I.cols + col];
+    I.glam[col] = -2.0 * (w - u);
+    fsh += lam[j] * u - 2.0 * w * lam[j];
+  }
+  fs[threadIdx.x] = fsh;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double f = 0.0;
+    for (int t = 0; t < 256; ++t) f += fs[t];
+    I.f[k] = I.alpha + f;
+  }
+  // Y_M = A D_lambda C for this model's columns
+  for (int e = threadIdx.x; e < n * r; e += 256) {
+    const int i = e % n, j = e / n;
+    double s = 0.0;
+    for (int l = 0; l < r; ++l) s = fma((double)A[(int64_t)l * I.lda + i] * lam[l], C[(int64_t)j * r + l], s);
+    I.YM[((int64_t)k * r + j) * n + i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gfinal: one block per (instance, column): G_A = -2d (Y - Y_M) lambda
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gfinal(const GInst<T>* insts, const GItem* items) {
+  const GItem it = items[blockIdx.x];
+  const GInst<T> I = insts[it.inst];
+  const int col = it.a;
+  const int64_t rp = (int64_t)I.nt * 16;
+  const double lj = I.lam[col];
+  for (int i = threadIdx.x; i < I.n; i += 256) {
+    double y = 0.0;
+    for (int sp = 0; sp < I.nsplit; ++sp) y += (double)I.Ypart[((int64_t)sp * rp + col) * I.ldy + i];
+    const double gval = -2.0 * I.d * (y - I.YM[(int64_t)col * I.n + i]) * lj;
+    I.G[(int64_t)col * I.ldg + i] = (T)gval;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gomega: Omega of every restart into the packed W of every instance
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gomega(const GInst<T>* insts, const uint64_t* seeds) {
+  const GInst<T> I = insts[blockIdx.y];
+  const uint64_t seed = seeds[blockIdx.y];
+  const int64_t nblk = ((int64_t)I.p + 15) / 16;
+  const int64_t total = nblk * I.nt * 256;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+    const int s = (int)(idx & 3);
+    const int lane = (int)((idx >> 2) & 63);
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t bt = idx >> 8;
+    const int t = (int)(bt % I.nt);
+    const int64_t b = bt / I.nt;
+    const int64_t l = 16 * b + Mfma<T>::row(g, s);
+    const int col = 16 * t + c;
+    double v = 0.0;
+    if (l < I.p && col < I.cols) {
+      const int k = col / I.r, j = col - k * I.r;
+      v = normal_at(seed, (uint32_t)k, STREAM_RRF_OMEGA, l + (int64_t)I.p * j);
+    }
+    I.Wp[idx] = (T)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_ggemm1(bool vec, int nitems, hipStream_t st, const GInst<T>* insts, const GItem* items) {
+  if (nitems <= 0) return;
+  if (vec) hipLaunchKernelGGL((k_ggemm1<T, true>), dim3(nitems), dim3(256), 0, st, insts, items);
+  else hipLaunchKernelGGL((k_ggemm1<T, false>), dim3(nitems), dim3(256), 0, st, insts, items);
+}
+template <typename T>
+void launch_gmodel(int nitems, hipStream_t st, const GInst<T>* insts, const GItem* items) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_gmodel<T>, dim3(nitems), dim3(256), 0, st, insts, items);
+}
+template <typename T>
+void launch_ggemm2(bool vec, int nitems, hipStream_t st, const GInst<T>* insts, const GItem* items) {
+  if (nitems <= 0) return;
+  if (vec) hipLaunchKernelGGL((k_ggemm2<T, true>), dim3(nitems), dim3(64), 0, st, insts, items);
+  else hipLaunchKernelGGL((k_ggemm2<T, false>), dim3(nitems), dim3(64), 0, st, insts, items);
+}
+template <typename T>
+void launch_gfinal(int nitems, hipStream_t st, const GInst<T>* insts, const GItem* items) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_gfinal<T>, dim3(nitems), dim3(256), 0, st, insts, items);
+}
+template <typename T>
+void launch_gomega(int maxchunks, int ninst, hipStream_t st, const GInst<T>* insts, const uint64_t* seeds) {
+  if (ninst <= 0) return;
+  hipLaunchKernelGGL(k_gomega<T>, dim3(maxchunks, ninst), dim3(256), 0, st, insts, seeds);
+}
+
+#define SYMTD_GG_INST(T)                                                                              \
+  template void launch_ggemm1<T>(bool, int, hipStream_t, const GInst<T>*, const GItem*);              \
+  template void launch_gmodel<T>(int, hipStream_t, const GInst<T>*, const GItem*);                    \
+  template void launch_ggemm2<T>(bool, int, hipStream_t, const GInst<T>*, const GItem*);              \
+  template void launch_gfinal<T>(int, hipStream_t, const GInst<T>*, const GItem*);                    \
+  template void launch_gomega<T>(int, int, hipStream_t, const GInst<T>*, const uint64_t*);
+SYMTD_GG_INST(float)
+SYMTD_GG_INST(double)
+
+}  // namespace symtd

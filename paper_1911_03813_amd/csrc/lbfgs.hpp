@@ -34,25 +34,31 @@ enum LbPhase : int { LB_START = 0, LB_BRACKET = 1, LB_ZOOM = 2, LB_DONE = 3 };
 enum LbAction : int { LB_NONE = 0, LB_START_DIR = 1, LB_TRIAL = 2, LB_ACCEPT_DIR = 3, LB_ACCEPT_FINAL = 4,
                       LB_RESTORE = 5 };
 
+// x holds A with leading dimension ld >= n (N = r + ld r); rows n .. ld-1 of
+// A stay zero (their gradient is zero), so the vector kernels need no masking.
 template <typename T>
 struct LbLane {
-  int64_t N; int n; int r;
+  int64_t N; int n; int r; int ld;
   int nb;                       // blocks of LB_CHUNK elements: ceil(N / LB_CHUNK)
+  int inst;                     // instance of a grouped solve (0 for a single problem)
   uint64_t seed; int restart;   // key and counter word of the lane's start draws
   const T* A0;                  // caller's start (leading dimension n), or null
   double* x; double* g; double* d; double* S; double* Y;   // S, Y: [m][N]
-  double* lam_t; T* A_t;        // trial point (evaluation inputs), A_t leading dimension n
-  const double* f_t; const double* glam_t; const T* G_t;   // evaluation outputs, G_t leading dimension n
+  double* lam_t; T* A_t;        // trial point (evaluation inputs), A_t leading dimension ld
+  const double* f_t; const double* glam_t; const T* G_t;   // evaluation outputs, G_t leading dimension ld
   double scale;                 // phi = f / scale
   double* part;                 // [nb][LB_ND] dot partials
   double* trace; int64_t trace_len;   // f after every accepted step (device), or null
-};
-
-struct LbParams {
+  struct LbState* state;        // this lane's state
+  int* done_flag;               // set to 1 when the lane stops, or null
+  // options
   int m;
   double pgtol, ftol;
   int64_t max_iters, max_evals;
-  int* done_count;              // lanes that reached LB_DONE (incremented once per lane)
+};
+
+struct LbParams {
+  int* done_count;              // lanes that reached LB_DONE (incremented once per lane), or null
 };
 
 // Per-lane state (device memory, zero-initialised = phase LB_START).
@@ -73,13 +79,11 @@ struct LbState {
 };
 
 template <typename T>
-void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbState* state,
-                    const LbParams& prm);
+void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev);
 template <typename T>
-void launch_lb_step(int lanes, hipStream_t st, const LbLane<T>* lanes_dev, LbState* state, const LbParams& prm);
+void launch_lb_step(int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbParams& prm);
 template <typename T>
-void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbState* state,
-                     const LbParams& prm);
+void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev);
 
 // Starts.  Gaussian: A_0 columns of normals (stream 1) into x; RRF: Omega
 // (stream 2) into the packed layout of the second product.  Then column
@@ -101,5 +105,10 @@ template <typename T>
 void launch_init_given(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev);
 template <typename T>
 void launch_norm_cols(int lanes, int r, hipStream_t st, const LbLane<T>* lanes_dev);
+// grouped randomized range finder: lane (instance i, restart k) takes columns
+// k r .. of instance i's second-product partials
+template <typename T> struct GInst;
+template <typename T>
+void launch_grrf_finish(int lanes, int rmax, hipStream_t st, const LbLane<T>* lanes_dev, const GInst<T>* insts);
 
 }  // namespace symtd

@@ -18,8 +18,10 @@
 //     iteration limit, then the evaluation limit.
 #include <math.h>
 
+#include "grouped.hpp"
 #include "kcommon.hpp"
 #include "lbfgs.hpp"
+#include "philox.hpp"
 
 namespace symtd {
 
@@ -67,14 +69,14 @@ __device__ __forceinline__ double wave_max(double v) {
 // as per-block partials (fixed order: thread-strided, then a fixed tree).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_lb_dots(const LbLane<T>* lanes, const LbState* state, LbParams prm) {
+__global__ __launch_bounds__(256) void k_lb_dots(const LbLane<T>* lanes) {
   const int L = blockIdx.y;
   const LbLane<T> ln = lanes[L];
   const int b = blockIdx.x;
   if (b >= ln.nb) return;
-  const int phase = state[L].phase;
+  const int phase = ln.state->phase;
   if (phase == LB_DONE) return;
-  const int cnt = state[L].count;
+  const int cnt = ln.state->count;
   double acc[LB_ND];
 #pragma unroll
   for (int i = 0; i < LB_ND; ++i) acc[i] = 0.0;
@@ -150,27 +152,31 @@ __device__ double zoom_trial(const LbState& s) {
   return t;
 }
 
-__device__ void begin_search(LbState& s, const LbParams& prm, double a1) {
+template <typename T>
+__device__ void begin_search(LbState& s, const LbLane<T>& ln, double a1) {
   s.phase = LB_BRACKET;
   s.a = a1;
   s.ls_i = 1;
   s.ls_evals = 0;
-  s.ls_limit = min((int64_t)LB_MAXLS, prm.max_evals - s.evals);
+  s.ls_limit = min((int64_t)LB_MAXLS, ln.max_evals - s.evals);
   s.a_prev = 0.0;
   s.f_prev = s.f;
   s.d_prev = s.dphi0;
 }
 
-__device__ void finish(LbState& s, const LbParams& prm, int reason, int action) {
+template <typename T>
+__device__ void finish(LbState& s, const LbLane<T>& ln, const LbParams& prm, int reason, int action) {
   s.phase = LB_DONE;
   s.reason = reason;
   s.action = action;
-  atomicAdd(prm.done_count, 1);
+  if (prm.done_count) atomicAdd(prm.done_count, 1);
+  if (ln.done_flag) *ln.done_flag = 1;
 }
 
 // a new direction at the accepted point (g = gt), using the pairs in the ring
-__device__ void new_direction(LbState& s, const LbParams& prm, const double* D) {
-  const int m = prm.m;
+template <typename T>
+__device__ void new_direction(LbState& s, const LbLane<T>& ln, const double* D) {
+  const int m = ln.m;
   const double gtgt = D[LB_GTGT];
   for (int i = 0; i < LB_MMAX; ++i) { s.cs[i] = 0.0; s.cy[i] = 0.0; }
   bool reset = s.count == 0;
@@ -226,15 +232,15 @@ __device__ void new_direction(LbState& s, const LbParams& prm, const double* D) 
     for (int i = 0; i < LB_MMAX; ++i) { s.cs[i] = 0.0; s.cy[i] = 0.0; }
     s.coef_g = -1.0;
     s.dphi0 = -gtgt;
-    begin_search(s, prm, fmin(1.0, 1.0 / sqrt(gtgt)));
+    begin_search(s, ln, fmin(1.0, 1.0 / sqrt(gtgt)));
   } else {
-    begin_search(s, prm, 1.0);
+    begin_search(s, ln, 1.0);
   }
 }
 
 template <typename T>
 __device__ void accept(LbState& s, const LbLane<T>& ln, const LbParams& prm, const double* D, double phi) {
-  const int m = prm.m;
+  const int m = ln.m;
   s.a_acc = s.a;
   s.iters += 1;
   const double sy = s.a_acc * D[LB_YTD];
@@ -243,13 +249,13 @@ __device__ void accept(LbState& s, const LbLane<T>& ln, const LbParams& prm, con
   s.f = phi;
   if (ln.trace && s.iters < ln.trace_len) ln.trace[s.iters] = phi * ln.scale;
   int reason = 0;
-  if (D[LB_MAXG] <= prm.pgtol) reason = EX_PGTOL;
-  else if (f_old - phi <= prm.ftol * fmax(fmax(fabs(f_old), fabs(phi)), 1.0)) reason = EX_FTOL;
-  else if (s.iters >= prm.max_iters) reason = EX_MAX_ITERS;
-  else if (s.evals >= prm.max_evals) reason = EX_MAX_EVALS;
+  if (D[LB_MAXG] <= ln.pgtol) reason = EX_PGTOL;
+  else if (f_old - phi <= ln.ftol * fmax(fmax(fabs(f_old), fabs(phi)), 1.0)) reason = EX_FTOL;
+  else if (s.iters >= ln.max_iters) reason = EX_MAX_ITERS;
+  else if (s.evals >= ln.max_evals) reason = EX_MAX_EVALS;
   if (reason) {
     s.store = 0;
-    finish(s, prm, reason, LB_ACCEPT_FINAL);
+    finish(s, ln, prm, reason, LB_ACCEPT_FINAL);
     return;
   }
   s.store = sy > LB_SKIP * yy;
@@ -272,20 +278,23 @@ __device__ void accept(LbState& s, const LbLane<T>& ln, const LbParams& prm, con
     s.gamma = sy / yy;
   }
   s.action = LB_ACCEPT_DIR;
-  new_direction(s, prm, D);
+  new_direction(s, ln, D);
 }
 
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbState* state, LbParams prm) {
+__global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbParams prm) {
   const int L = blockIdx.x;
-  LbState& s = state[L];
+  const LbLane<T> ln = lanes[L];
+  LbState& s = *ln.state;
   if (s.phase == LB_DONE) {
-    if (threadIdx.x == 0) s.action = LB_NONE;
+    if (threadIdx.x == 0) {
+      s.action = LB_NONE;
+      if (ln.done_flag) *ln.done_flag = 1;   // kept raised (tables may have been rebuilt)
+    }
     return;
   }
-  const LbLane<T> ln = lanes[L];
   __shared__ double D[LB_ND];
   if (threadIdx.x < LB_ND) {
     const int i = threadIdx.x;
@@ -307,9 +316,9 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbState*
   if (s.phase == LB_START) {
     s.f = phi;
     if (ln.trace && ln.trace_len > 0) ln.trace[0] = phi * ln.scale;
-    if (!(isfinite(phi) && isfinite(D[LB_GTGT]))) { finish(s, prm, EX_NONFINITE, LB_RESTORE); return; }
-    if (D[LB_MAXG] <= prm.pgtol) { finish(s, prm, EX_PGTOL, LB_RESTORE); return; }
-    if (s.evals >= prm.max_evals) { finish(s, prm, EX_MAX_EVALS, LB_RESTORE); return; }
+    if (!(isfinite(phi) && isfinite(D[LB_GTGT]))) { finish(s, ln, prm, EX_NONFINITE, LB_RESTORE); return; }
+    if (D[LB_MAXG] <= ln.pgtol) { finish(s, ln, prm, EX_PGTOL, LB_RESTORE); return; }
+    if (s.evals >= ln.max_evals) { finish(s, ln, prm, EX_MAX_EVALS, LB_RESTORE); return; }
     s.count = 0;
     s.head = 0;
     s.store = 0;
@@ -317,7 +326,7 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbState*
     s.coef_g = -1.0;
     s.dphi0 = -D[LB_GTGT];
     s.action = LB_START_DIR;
-    begin_search(s, prm, fmin(1.0, 1.0 / sqrt(D[LB_GTGT])));
+    begin_search(s, ln, fmin(1.0, 1.0 / sqrt(D[LB_GTGT])));
     return;
   }
 
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbState*
       to_zoom = true;
     } else {
       if (s.ls_evals >= s.ls_limit) {
-        finish(s, prm, s.evals >= prm.max_evals ? EX_MAX_EVALS : EX_LINESEARCH, LB_RESTORE);
+        finish(s, ln, prm, s.evals >= ln.max_evals ? EX_MAX_EVALS : EX_LINESEARCH, LB_RESTORE);
         return;
       }
       s.a_prev = s.a; s.f_prev = phi; s.d_prev = gtd;
@@ -366,7 +375,7 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbState*
   if (to_zoom) {
     if (s.ls_evals >= s.ls_limit ||
         fabs(s.hi_a - s.lo_a) <= LB_COLLAPSE * fmax(fabs(s.lo_a), fabs(s.hi_a))) {
-      finish(s, prm, s.evals >= prm.max_evals ? EX_MAX_EVALS : EX_LINESEARCH, LB_RESTORE);
+      finish(s, ln, prm, s.evals >= ln.max_evals ? EX_MAX_EVALS : EX_LINESEARCH, LB_RESTORE);
       return;
     }
     s.phase = LB_ZOOM;
@@ -380,12 +389,12 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbState*
 // point (or, when it has finished, its final point) into the evaluation inputs
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes, const LbState* state, LbParams prm) {
+__global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes) {
   const int L = blockIdx.y;
   const LbLane<T> ln = lanes[L];
   const int b = blockIdx.x;
   if (b >= ln.nb) return;
-  const LbState& s = state[L];
+  const LbState& s = *ln.state;
   const int act = s.action;
   if (act == LB_NONE) return;
   const double a = s.a, a_acc = s.a_acc, coef_g = s.coef_g;
@@ -443,37 +452,6 @@ __global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes, const 
 // ---------------------------------------------------------------------------
 // starts
 // ---------------------------------------------------------------------------
-namespace {
-
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-  for (int rnd = 0; rnd < 10; ++rnd) {
-    if (rnd > 0) { k0 += W0; k1 += W1; }
-    const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
-    const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-  }
-}
-
-// normal number e of (seed, restart, stream)
-__device__ double normal_at(uint64_t seed, uint32_t restart, uint32_t stream, int64_t e) {
-  const uint64_t blk = (uint64_t)e >> 2;
-  uint32_t c[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), restart, stream};
-  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-  const int q = (int)(e & 3);
-  const int pr = q >> 1;
-  const double u1 = ((double)c[2 * pr] + 0.5) * (1.0 / 4294967296.0);
-  const double u2 = ((double)c[2 * pr + 1] + 0.5) * (1.0 / 4294967296.0);
-  const double rad = sqrt(-2.0 * log(u1));
-  const double th = 2.0 * M_PI * u2;
-  return (q & 1) ? rad * sin(th) : rad * cos(th);
-}
-
-}  // namespace
-
-constexpr uint32_t STREAM_GAUSS_A0 = 1, STREAM_RRF_OMEGA = 2;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_gauss(const LbLane<T>* lanes) {
@@ -483,7 +461,12 @@ __global__ __launch_bounds__(256) void k_init_gauss(const LbLane<T>* lanes) {
   for (int k = 0; k < LB_CHUNK / 256; ++k) {
     const int64_t e = (int64_t)blockIdx.x * LB_CHUNK + k * 256 + threadIdx.x;
     if (e >= ln.N) break;
-    ln.x[e] = e < ln.r ? 1.0 : normal_at(ln.seed, (uint32_t)ln.restart, STREAM_GAUSS_A0, e - ln.r);
+    double v = 1.0;
+    if (e >= ln.r) {
+      const int64_t q = e - ln.r, j = q / ln.ld, i = q - j * ln.ld;
+      v = i < ln.n ? normal_at(ln.seed, (uint32_t)ln.restart, STREAM_GAUSS_A0, i + j * ln.n) : 0.0;
+    }
+    ln.x[e] = v;
   }
 }
 
@@ -495,7 +478,11 @@ __global__ __launch_bounds__(256) void k_init_given(const LbLane<T>* lanes) {
   for (int k = 0; k < LB_CHUNK / 256; ++k) {
     const int64_t e = (int64_t)blockIdx.x * LB_CHUNK + k * 256 + threadIdx.x;
     if (e >= ln.N) break;
-    const double v = e < ln.r ? 1.0 : (double)ln.A0[e - ln.r];
+    double v = 1.0;
+    if (e >= ln.r) {
+      const int64_t q = e - ln.r, j = q / ln.ld, i = q - j * ln.ld;
+      v = i < ln.n ? (double)ln.A0[i + j * ln.n] : 0.0;
+    }
     ln.x[e] = v;
     write_trial(ln, e, v);
   }
@@ -520,14 +507,14 @@ __global__ __launch_bounds__(256) void k_norm_cols(const LbLane<T>* lanes) {
   const int L = blockIdx.y, j = blockIdx.x;
   const LbLane<T> ln = lanes[L];
   if (j >= ln.r) return;
-  double* col = ln.x + ln.r + (int64_t)j * ln.n;
+  double* col = ln.x + ln.r + (int64_t)j * ln.ld;
   double ss = 0.0;
   for (int i = threadIdx.x; i < ln.n; i += 256) ss = fma(col[i], col[i], ss);
   const double nrm = sqrt(block_sum(ss, sm));
-  for (int i = threadIdx.x; i < ln.n; i += 256) {
-    const double v = col[i] / nrm;
+  for (int i = threadIdx.x; i < ln.ld; i += 256) {
+    const double v = i < ln.n ? col[i] / nrm : 0.0;
     col[i] = v;
-    ln.A_t[(int64_t)j * ln.n + i] = (T)v;
+    ln.A_t[(int64_t)j * ln.ld + i] = (T)v;
   }
   if (threadIdx.x == 0) {
     ln.x[j] = 1.0;
@@ -568,7 +555,7 @@ __global__ __launch_bounds__(256) void k_rrf_finish(const LbLane<T>* lanes, cons
   const LbLane<T> ln = lanes[L];
   if (j >= ln.r) return;
   const int64_t colg = (int64_t)ln.restart * ln.r + j;
-  double* col = ln.x + ln.r + (int64_t)j * ln.n;
+  double* col = ln.x + ln.r + (int64_t)j * ln.ld;
   double ss = 0.0;
   for (int i = threadIdx.x; i < ln.n; i += 256) {
     double y = 0.0;
@@ -577,10 +564,43 @@ __global__ __launch_bounds__(256) void k_rrf_finish(const LbLane<T>* lanes, cons
     ss = fma(y, y, ss);
   }
   const double nrm = sqrt(block_sum(ss, sm));
-  for (int i = threadIdx.x; i < ln.n; i += 256) {
-    const double v = col[i] / nrm;
+  for (int i = threadIdx.x; i < ln.ld; i += 256) {
+    const double v = i < ln.n ? col[i] / nrm : 0.0;
     col[i] = v;
-    ln.A_t[(int64_t)j * ln.n + i] = (T)v;
+    ln.A_t[(int64_t)j * ln.ld + i] = (T)v;
+  }
+  if (threadIdx.x == 0) {
+    ln.x[j] = 1.0;
+    ln.lam_t[j] = 1.0;
+  }
+}
+
+// grouped form: the partials of the lane's instance ([split][nt*16][ldy])
+template <typename T>
+__global__ __launch_bounds__(256) void k_grrf_finish(const LbLane<T>* lanes, const GInst<T>* insts) {
+  __shared__ double sm[4];
+  const int L = blockIdx.y, j = blockIdx.x;
+  const LbLane<T> ln = lanes[L];
+  if (j >= ln.r) return;
+  const GInst<T>& I = insts[ln.inst];
+  const int64_t colg = (int64_t)ln.restart * ln.r + j;
+  const int64_t rp = (int64_t)I.nt * 16;
+  const int nsplit = I.nsplit;
+  const int64_t ldy = I.ldy;
+  const T* Yp = I.Ypart;
+  double* col = ln.x + ln.r + (int64_t)j * ln.ld;
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < ln.n; i += 256) {
+    double y = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) y += (double)Yp[((int64_t)sp * rp + colg) * ldy + i];
+    col[i] = y;
+    ss = fma(y, y, ss);
+  }
+  const double nrm = sqrt(block_sum(ss, sm));
+  for (int i = threadIdx.x; i < ln.ld; i += 256) {
+    const double v = i < ln.n ? col[i] / nrm : 0.0;
+    col[i] = v;
+    ln.A_t[(int64_t)j * ln.ld + i] = (T)v;
   }
   if (threadIdx.x == 0) {
     ln.x[j] = 1.0;
@@ -592,18 +612,16 @@ __global__ __launch_bounds__(256) void k_rrf_finish(const LbLane<T>* lanes, cons
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbState* state,
-                    const LbParams& prm) {
-  hipLaunchKernelGGL(k_lb_dots<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev, state, prm);
+void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev) {
+  hipLaunchKernelGGL(k_lb_dots<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev);
 }
 template <typename T>
-void launch_lb_step(int lanes, hipStream_t st, const LbLane<T>* lanes_dev, LbState* state, const LbParams& prm) {
-  hipLaunchKernelGGL(k_lb_step<T>, dim3(lanes), dim3(64), 0, st, lanes_dev, state, prm);
+void launch_lb_step(int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbParams& prm) {
+  hipLaunchKernelGGL(k_lb_step<T>, dim3(lanes), dim3(64), 0, st, lanes_dev, prm);
 }
 template <typename T>
-void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbState* state,
-                     const LbParams& prm) {
-  hipLaunchKernelGGL(k_lb_apply<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev, state, prm);
+void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev) {
+  hipLaunchKernelGGL(k_lb_apply<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev);
 }
 template <typename T>
 void launch_init_gauss(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev) {
@@ -618,6 +636,10 @@ void launch_norm_cols(int lanes, int r, hipStream_t st, const LbLane<T>* lanes_d
   hipLaunchKernelGGL(k_norm_cols<T>, dim3(r, lanes), dim3(256), 0, st, lanes_dev);
 }
 template <typename T>
+void launch_grrf_finish(int lanes, int rmax, hipStream_t st, const LbLane<T>* lanes_dev, const GInst<T>* insts) {
+  hipLaunchKernelGGL(k_grrf_finish<T>, dim3(rmax, lanes), dim3(256), 0, st, lanes_dev, insts);
+}
+template <typename T>
 void launch_omega_packed(dim3 grid, hipStream_t st, T* Wp, int64_t p, int r, int restarts, int nt_tot,
                          int64_t nblk, uint64_t seed) {
   const int64_t total = nblk * nt_tot * 256;
@@ -630,12 +652,13 @@ void launch_rrf_finish(int lanes, int r, hipStream_t st, const LbLane<T>* lanes_
 }
 
 #define SYMTD_LB_INST(T)                                                                                       \
-  template void launch_lb_dots<T>(int, int, hipStream_t, const LbLane<T>*, const LbState*, const LbParams&);    \
-  template void launch_lb_step<T>(int, hipStream_t, const LbLane<T>*, LbState*, const LbParams&);               \
-  template void launch_lb_apply<T>(int, int, hipStream_t, const LbLane<T>*, const LbState*, const LbParams&);   \
+  template void launch_lb_dots<T>(int, int, hipStream_t, const LbLane<T>*);                                    \
+  template void launch_lb_step<T>(int, hipStream_t, const LbLane<T>*, const LbParams&);                         \
+  template void launch_lb_apply<T>(int, int, hipStream_t, const LbLane<T>*);                                    \
   template void launch_init_gauss<T>(int, int, hipStream_t, const LbLane<T>*);                                  \
   template void launch_init_given<T>(int, int, hipStream_t, const LbLane<T>*);                                  \
   template void launch_norm_cols<T>(int, int, hipStream_t, const LbLane<T>*);                                   \
+  template void launch_grrf_finish<T>(int, int, hipStream_t, const LbLane<T>*, const GInst<T>*);                 \
   template void launch_omega_packed<T>(dim3, hipStream_t, T*, int64_t, int, int, int, int64_t, uint64_t);      \
   template void launch_rrf_finish<T>(int, int, hipStream_t, const LbLane<T>*, const T*, int64_t, int64_t, int);
 SYMTD_LB_INST(float)

@@ -480,6 +480,7 @@ symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value)
     case SYMTD_TUNE_G1_BLOCKS: ctx->tune_g1_blocks = value; return SYMTD_OK;
     case SYMTD_TUNE_G2_SPLITS: ctx->tune_g2_splits = value; return SYMTD_OK;
     case SYMTD_TUNE_SERIAL: ctx->tune_serial = value; return SYMTD_OK;
+    case SYMTD_TUNE_GRAPH: ctx->tune_graph = value; return SYMTD_OK;
   }
   return ctx->fail(SYMTD_EINVAL, "unknown tuning key %d", (int)key);
 }

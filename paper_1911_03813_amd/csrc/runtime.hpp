@@ -27,6 +27,7 @@ struct symtd_ctx {
   int* dev_err = nullptr;
   // work-split overrides (0 = automatic)
   int64_t tune_g1_blocks = 0, tune_g2_splits = 0, tune_serial = 0;
+  int64_t tune_graph = 1;   // grouped engine: replay captured steps (1) or launch eagerly (0)
 
   // per-kernel timing (symtd_profile_*)
   struct Pending { int which; hipEvent_t start, stop; hipStream_t st; };
@@ -61,6 +62,10 @@ template <typename T> struct LbLane;
 template <typename T>
 symtd_status run_rrf(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, int64_t n, int64_t p, int64_t r,
                      int restarts, uint64_t seed, const LbLane<T>* lanes_dev);
+
+// argument checks of a solve request (problem, options, result buffers)
+symtd_status check_solve(symtd_ctx* ctx, const symtd_problem* pb, const symtd_solve_opts* o,
+                         const symtd_solve_result* out);
 
 // alpha = ||X||^2 into one device fp64 value.  Arguments checked by the caller.
 template <typename S>

@@ -63,7 +63,12 @@ struct SolveLayout {
   }
 };
 
-symtd_status check_opts(symtd_ctx* ctx, const symtd_problem* pb, const symtd_solve_opts* o, symtd_solve_result* out) {
+}  // namespace
+
+namespace symtd {
+
+symtd_status check_solve(symtd_ctx* ctx, const symtd_problem* pb, const symtd_solve_opts* o,
+                         const symtd_solve_result* out) {
   if (!pb || !o || !out) return ctx->fail(SYMTD_EINVAL, "null problem, options or result");
   if (pb->r < 1 || pb->r > 0x7fffffffLL) return ctx->fail(SYMTD_EINVAL, "rank r=%lld must be >= 1", (long long)pb->r);
   if (o->m < 1 || o->m > LB_MMAX) return ctx->fail(SYMTD_EINVAL, "memory m=%d outside [1, %d]", o->m, LB_MMAX);
@@ -84,8 +89,15 @@ symtd_status check_opts(symtd_ctx* ctx, const symtd_problem* pb, const symtd_sol
   const size_t esz = pb->dt == SYMTD_F64 ? 8 : 4;
   if (((uintptr_t)out->A % esz) || ((uintptr_t)out->lambda % 8)) return ctx->fail(SYMTD_EALIGN, "result A or lambda misaligned");
   if (o->A0 && ((uintptr_t)o->A0 % esz)) return ctx->fail(SYMTD_EALIGN, "A0 misaligned");
+  symtd_status s = ctx->check_common(pb->dt, pb->V, pb->ldv, pb->nu, pb->n, pb->p, pb->d);
+  if (s != SYMTD_OK) return s;
+  if ((int64_t)pb->r * o->restarts > 0x7fffffffLL) return ctx->fail(SYMTD_EINVAL, "r * restarts too large");
   return SYMTD_OK;
 }
+
+}  // namespace symtd
+
+namespace {
 
 template <typename T>
 symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, const symtd_solve_opts& o,
@@ -126,7 +138,7 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
   std::vector<LbLane<T>> lanes(R);
   for (int k = 0; k < R; ++k) {
     LbLane<T>& L = lanes[k];
-    L.N = N; L.n = (int)n; L.r = (int)r; L.nb = nb;
+    L.N = N; L.n = (int)n; L.r = (int)r; L.ld = (int)n; L.nb = nb; L.inst = 0;
     L.seed = o.seed; L.restart = k;
     L.A0 = o.A0 ? (const T*)o.A0 + (size_t)k * r * n : nullptr;
     L.x = Lay.x + (size_t)k * N; L.g = Lay.g + (size_t)k * N; L.d = Lay.dd + (size_t)k * N;
@@ -137,6 +149,9 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
     L.part = Lay.part + (size_t)k * nb * LB_ND;
     L.trace = trace_len > 0 ? Lay.trace + (size_t)k * trace_len : nullptr;
     L.trace_len = trace_len;
+    L.state = Lay.states + k;
+    L.done_flag = nullptr;
+    L.m = m; L.pgtol = o.pgtol; L.ftol = o.ftol; L.max_iters = o.max_iters; L.max_evals = o.max_evals;
   }
   const size_t vec_bytes = (size_t)R * N * sizeof(double);
   if ((e = hipMemcpyAsync(Lay.lanes, lanes.data(), sizeof(LbLane<T>) * R, hipMemcpyHostToDevice, st)) != hipSuccess ||
@@ -160,7 +175,7 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
   }
   if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "start kernels");
 
-  LbParams prm{m, o.pgtol, o.ftol, o.max_iters, o.max_evals, Lay.done};
+  LbParams prm{Lay.done};
   // steps between polls: enough to keep the queue ahead of the device, few
   // enough that little work is done after the last lane has stopped
   const double work = 4.0 * (double)n * (double)p * (double)r * R;
@@ -172,9 +187,9 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
       if ((s = run_fg<T>(ctx, st, V, pb.ldv, pb.nu, n, p, Lay.A_t, n, Lay.lam_t, r, R, d, alpha, Lay.f_t, Lay.glam_t,
                          Lay.G_t, n)) != SYMTD_OK)
         return s;
-      launch_lb_dots<T>(nb, R, st, Lay.lanes, Lay.states, prm);
-      launch_lb_step<T>(R, st, Lay.lanes, Lay.states, prm);
-      launch_lb_apply<T>(nb, R, st, Lay.lanes, Lay.states, prm);
+      launch_lb_dots<T>(nb, R, st, Lay.lanes);
+      launch_lb_step<T>(R, st, Lay.lanes, prm);
+      launch_lb_apply<T>(nb, R, st, Lay.lanes);
       ++steps;
     }
     if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "solver kernels");
@@ -247,10 +262,8 @@ symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb, 
                          symtd_solve_result* out) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
-  symtd_status s = check_opts(ctx, pb, o, out);
+  symtd_status s = check_solve(ctx, pb, o, out);
   if (s != SYMTD_OK) return s;
-  if ((s = ctx->check_common(pb->dt, pb->V, pb->ldv, pb->nu, pb->n, pb->p, pb->d)) != SYMTD_OK) return s;
-  if ((int64_t)pb->r * o->restarts > 0x7fffffffLL) return ctx->fail(SYMTD_EINVAL, "r * restarts too large");
   if ((s = ctx->set_device()) != SYMTD_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if (pb->dt == SYMTD_F64) return run_solve<double>(ctx, st, *pb, *o, out);

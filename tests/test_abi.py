@@ -69,6 +69,8 @@ def test_struct_layouts_match_header(tmp_path):
         "symtd_problem": (S.Problem, ["dt", "V", "ldv", "nu", "n", "p", "d", "r"]),
         "symtd_solve_opts": (S.SolveOpts, ["prec", "m", "pgtol", "ftol", "max_iters", "max_evals", "restarts",
                                            "seed", "init", "alpha_mode", "alpha", "A0", "check_every"]),
+        "symtd_fg_item": (S.FgItem, ["V", "ldv", "nu", "n", "p", "d", "A", "lda", "lambda", "r", "models",
+                                     "alpha", "f", "g_lambda", "G_A", "ldg"]),
         "symtd_solve_result": (S.SolveResult, ["A", "lda", "lambda", "f_restarts", "iters_restarts",
                                                "evals_restarts", "exit_restarts", "f_trace", "trace_len", "f",
                                                "alpha", "rel_err", "iters", "evals", "exit_reason",

@@ -256,6 +256,72 @@ symtd_status symtd_fg_batched(symtd_ctx* ctx, void* stream, symtd_dtype dt, symt
 symtd_status symtd_solve_batched(symtd_ctx* ctx, void* stream, int64_t count, const symtd_problem* pbs,
                                  const symtd_solve_opts* opts, symtd_solve_result* outs);
 
+/* ------------------------------------------------------------------------
+ * Served form: a request loop over the grouped engine (continuous batching).
+ *
+ * A server owns its own context on `device`, a device memory budget
+ * (`memory_bytes`, the arena that admitted requests live in) and a host
+ * thread that runs the engine.  symtd_server_submit copies the request's V
+ * and nu (device pointers) into a private staging copy before it returns, so
+ * the caller may reuse them at once, and queues it.  The server thread admits
+ * queued requests in arrival order while their footprint (padded V, the
+ * evaluation buffers and the L-BFGS state of their restarts) fits into the
+ * free memory, runs evaluation steps for every admitted request together,
+ * and moves finished requests to the completion queue; requests that arrive
+ * while others run join at the next step boundary.  Each result is the same
+ * bits as the same request solved alone on the grouped engine
+ * (symtd_solve_batched with one problem).  All requests of a server share
+ * its dtype and precision.  submit, poll, cancel and stats may be called
+ * from any host thread.
+ * ------------------------------------------------------------------------ */
+typedef struct symtd_server symtd_server;
+
+typedef struct symtd_server_opts {
+  int device;
+  symtd_dtype dt;
+  symtd_prec prec;
+  size_t memory_bytes;      /* device memory for admitted requests */
+  int check_every;          /* evaluation steps between polls (0 = automatic) */
+  int use_graph;            /* replay captured steps (1) or launch eagerly (0) */
+} symtd_server_opts;
+
+typedef struct symtd_server_result {
+  uint64_t id;
+  symtd_status status;      /* SYMTD_OK, or the error that ended this request */
+  double f, alpha, rel_err;
+  int64_t iters, evals;     /* of the best restart */
+  int exit_reason, best_restart;
+  int64_t n, r;
+  double* A;                /* host, n x r column-major, owned by the result */
+  double* lambda;           /* host, r values, owned by the result */
+  double t_submit, t_admit, t_done;   /* seconds since the server started */
+} symtd_server_result;
+
+typedef struct symtd_server_stats {
+  int64_t submitted, admitted, completed, cancelled, queued, running;
+  int64_t steps;            /* evaluation steps run */
+  size_t memory_used, memory_bytes;
+} symtd_server_stats;
+
+symtd_status symtd_server_create(const symtd_server_opts* opts, symtd_server** out);
+/* Queue one request (opts->A0 must be NULL; trace outputs are not kept).
+ * SYMTD_EREJECTED if its footprint exceeds the whole memory budget. */
+symtd_status symtd_server_submit(symtd_server* srv, const symtd_problem* pb, const symtd_solve_opts* opts,
+                                 uint64_t* id);
+/* Move up to `max` finished results into `out` (in completion order); waits up
+ * to timeout_ms (0 = do not wait, < 0 = wait until at least one is ready or
+ * nothing is pending). */
+symtd_status symtd_server_poll(symtd_server* srv, symtd_server_result* out, int32_t max, int32_t* n_out,
+                               int32_t timeout_ms);
+/* Cancel a request that is still queued (SYMTD_EINVAL if it is not). */
+symtd_status symtd_server_cancel(symtd_server* srv, uint64_t id);
+symtd_status symtd_server_stats_get(symtd_server* srv, symtd_server_stats* out);
+const char* symtd_server_last_error(const symtd_server* srv);
+/* Free the host arrays of a result. */
+void symtd_server_result_release(symtd_server_result* res);
+/* Stop the thread (running requests are abandoned) and free everything. */
+void symtd_server_destroy(symtd_server* srv);
+
 /*
  * Work-split tuning of the evaluation kernels (used by the autotuner and by
  * tests that force particular splits). Keys:

@@ -59,6 +59,29 @@ class FgItem(ctypes.Structure):
                 ("G_A", ctypes.c_void_p), ("ldg", ctypes.c_int64)]
 
 
+class ServerOpts(ctypes.Structure):
+    """symtd_server_opts"""
+    _fields_ = [("device", ctypes.c_int), ("dt", ctypes.c_int), ("prec", ctypes.c_int),
+                ("memory_bytes", ctypes.c_size_t), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class ServerResult(ctypes.Structure):
+    """symtd_server_result"""
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int), ("f", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("rel_err", ctypes.c_double), ("iters", ctypes.c_int64),
+                ("evals", ctypes.c_int64), ("exit_reason", ctypes.c_int), ("best_restart", ctypes.c_int),
+                ("n", ctypes.c_int64), ("r", ctypes.c_int64), ("A", ctypes.POINTER(ctypes.c_double)),
+                ("lam", ctypes.POINTER(ctypes.c_double)), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    """symtd_server_stats"""
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("memory_used", ctypes.c_size_t), ("memory_bytes", ctypes.c_size_t)]
+
+
 class SolveResult(ctypes.Structure):
     """symtd_solve_result"""
     _fields_ = [("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("lam", ctypes.c_void_p),
@@ -89,6 +112,14 @@ SIGNATURES = {
     "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
     "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
     "symtd_fg_batched": (_int, [_vp, _vp, _int, _int, _i64, _c.POINTER(FgItem)]),
+    "symtd_server_create": (_int, [_c.POINTER(ServerOpts), _c.POINTER(_vp)]),
+    "symtd_server_submit": (_int, [_vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(_c.c_uint64)]),
+    "symtd_server_poll": (_int, [_vp, _c.POINTER(ServerResult), _c.c_int32, _c.POINTER(_c.c_int32), _c.c_int32]),
+    "symtd_server_cancel": (_int, [_vp, _c.c_uint64]),
+    "symtd_server_stats_get": (_int, [_vp, _c.POINTER(ServerStats)]),
+    "symtd_server_last_error": (_c.c_char_p, [_vp]),
+    "symtd_server_result_release": (None, [_c.POINTER(ServerResult)]),
+    "symtd_server_destroy": (None, [_vp]),
     "symtd_solve_batched": (_int, [_vp, _vp, _i64, _c.POINTER(Problem), _c.POINTER(SolveOpts),
                                    _c.POINTER(SolveResult)]),
     "symtd_profile_enable": (_int, [_vp, _int]),
@@ -384,6 +415,78 @@ def symtd_fg_batched(ctx: Context, items, stream=None):
     prec = PREC_FP64 if dt == F64 else PREC_FP32
     _check(ctx, lib().symtd_fg_batched(ctx.handle, _stream(stream), dt, prec, len(items), arr))
     return outs
+
+
+class Server:
+    """A symtd server (symtd_server_*): continuous batching of solve requests.
+
+    submit(V, nu, d, r, **symtd_solve options) -> request id; poll() returns
+    finished results as dicts with host (numpy) A and lam.
+    """
+
+    def __init__(self, device: int = 0, dtype=None, memory_bytes: int = 8 << 30, check_every: int = 0,
+                 use_graph: bool = True):
+        import torch
+        dtype = torch.float32 if dtype is None else dtype
+        dt = F64 if dtype == torch.float64 else F32
+        self.dtype = dtype
+        o = ServerOpts(int(device), dt, PREC_FP64 if dt == F64 else PREC_FP32, int(memory_bytes),
+                       int(check_every), int(bool(use_graph)))
+        h = _vp()
+        st = lib().symtd_server_create(ctypes.byref(o), ctypes.byref(h))
+        if st != SYMTD_OK:
+            raise SymtdError(st, "symtd_server_create failed")
+        self._h = h
+
+    def _err(self, st):
+        if st != SYMTD_OK:
+            msg = lib().symtd_server_last_error(self._h)
+            raise SymtdError(st, msg.decode() if msg else "")
+
+    def submit(self, V, nu, d: int, r: int, **opts) -> int:
+        call = _SolveCall(V, nu, d, r, **opts)
+        rid = ctypes.c_uint64()
+        self._err(lib().symtd_server_submit(self._h, ctypes.byref(call.pb), ctypes.byref(call.opts),
+                                            ctypes.byref(rid)))
+        return int(rid.value)
+
+    def poll(self, max_results: int = 64, timeout_ms: int = 0):
+        import numpy as np
+        buf = (ServerResult * max_results)()
+        n = ctypes.c_int32()
+        self._err(lib().symtd_server_poll(self._h, buf, int(max_results), ctypes.byref(n), int(timeout_ms)))
+        out = []
+        for i in range(n.value):
+            rres = buf[i]
+            d = {k: getattr(rres, k) for k in ("id", "status", "f", "alpha", "rel_err", "iters", "evals",
+                                                 "exit_reason", "best_restart", "n", "r", "t_submit", "t_admit",
+                                                 "t_done")}
+            if rres.status == SYMTD_OK:
+                nn, rr = rres.n, rres.r
+                d["A"] = np.ctypeslib.as_array(rres.A, shape=(nn * rr,)).reshape(rr, nn).T.copy()
+                d["lam"] = np.ctypeslib.as_array(rres.lam, shape=(rr,)).copy()
+            lib().symtd_server_result_release(ctypes.byref(buf[i]))
+            out.append(d)
+        return out
+
+    def cancel(self, rid: int):
+        self._err(lib().symtd_server_cancel(self._h, ctypes.c_uint64(rid)))
+
+    def stats(self):
+        s = ServerStats()
+        self._err(lib().symtd_server_stats_get(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().symtd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def symtd_normX(ctx: Context, V, nu, d: int, out=None, stream=None):

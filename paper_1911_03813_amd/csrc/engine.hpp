@@ -498,13 +498,9 @@ class GroupEngine {
     d_lanes_ = t.take<LbLane<T>>(lanes.size() + 1);
     d_lane_done_ = t.take<int>(lanes.size() + 1);
     for (size_t L = 0; L < lanes.size(); ++L) lanes[L].done_flag = d_lane_done_ + L;
-    // lanes that already stopped keep their flag (their state says so as well)
-    if (!init) {
-      size_t L = 0;
-      for (auto* I : set) {
-        for (int k = 0; k < I->R; ++k, ++L) done0[L] = I->done ? 1 : lane_flag(I, k);
-      }
-    }
+    // every flag starts low in a new table: a lane that has stopped raises
+    // its flag again at each step (its state is final), so nothing is lost
+    for (size_t L = 0; L < done0.size(); ++L) done0[L] = 0;
     // the copies below read host vectors; the stream is synchronised before
     // they go out of scope, since table uploads are rare
     if ((e = hipMemcpyAsync(d_ginst_, gi.data(), sizeof(GInst<T>) * gi.size(), hipMemcpyHostToDevice, st_)) != hipSuccess ||
@@ -515,20 +511,7 @@ class GroupEngine {
         (e = hipMemcpyAsync(d_lane_done_, done0.data(), sizeof(int) * done0.size(), hipMemcpyHostToDevice, st_)) != hipSuccess ||
         (e = hipStreamSynchronize(st_)) != hipSuccess)
       return ctx_->hip_fail(e, "engine table upload");
-    if (!init) {
-      // remember where each live instance's lanes start (for lane_flag)
-      size_t L = 0;
-      lane_base_.clear();
-      for (auto* I : set) { lane_base_[I] = L; L += I->R; }
-      lane_done_host_.assign(done0.begin(), done0.end());
-    }
     return SYMTD_OK;
-  }
-
-  int lane_flag(EngineInst<T>* I, int k) const {
-    auto it = lane_base_.find(I);
-    if (it == lane_base_.end() || it->second + k >= lane_done_host_.size()) return 0;
-    return lane_done_host_[it->second + k];
   }
 
   void drop_graph() {
@@ -565,7 +548,6 @@ class GroupEngine {
   int off_g1_ = 0, n_g1_ = 0, off_gm_ = 0, n_gm_ = 0, off_g2_ = 0, n_g2_ = 0, off_gf_ = 0, n_gf_ = 0;
   int nlanes_ = 0, nbmax_ = 1;
   std::vector<int> lane_done_host_;
-  std::map<EngineInst<T>*, size_t> lane_base_;
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;
   int64_t steps_ = 0;

@@ -71,6 +71,12 @@ def test_struct_layouts_match_header(tmp_path):
                                            "seed", "init", "alpha_mode", "alpha", "A0", "check_every"]),
         "symtd_fg_item": (S.FgItem, ["V", "ldv", "nu", "n", "p", "d", "A", "lda", "lambda", "r", "models",
                                      "alpha", "f", "g_lambda", "G_A", "ldg"]),
+        "symtd_server_opts": (S.ServerOpts, ["device", "dt", "prec", "memory_bytes", "check_every", "use_graph"]),
+        "symtd_server_result": (S.ServerResult, ["id", "status", "f", "alpha", "rel_err", "iters", "evals",
+                                                 "exit_reason", "best_restart", "n", "r", "A", "lambda",
+                                                 "t_submit", "t_admit", "t_done"]),
+        "symtd_server_stats": (S.ServerStats, ["submitted", "admitted", "completed", "cancelled", "queued",
+                                               "running", "steps", "memory_used", "memory_bytes"]),
         "symtd_solve_result": (S.SolveResult, ["A", "lda", "lambda", "f_restarts", "iters_restarts",
                                                "evals_restarts", "exit_restarts", "f_trace", "trace_len", "f",
                                                "alpha", "rel_err", "iters", "evals", "exit_reason",

@@ -1,16 +1,27 @@
-"""Benchmark of the objective-and-gradient evaluation (Algorithm 2).
+"""Benchmark of the objective-and-gradient evaluation (Algorithm 2), with the
+batched and served solve forms beside it.
 
-One step = one symtd_fg call: f, g_lambda and G_A for the large single
-instance d=3, n=1000, r=100, p=100000 (Gaussian-mixture observations,
+Headline: one step = one symtd_fg call, f, g_lambda and G_A for the large
+single instance d=3, n=1000, r=100, p=100000 (Gaussian-mixture observations,
 sigma=1e-2, nu=1/p), fp32 storage and fp32 matrix-core products with fp64
 reductions and assembly.  Inputs are resident in device memory before the
-timed region starts.
+timed region starts.  The JSON line carries the throughput (evals/s), the
+roofline figures of the dominant kernel (timed with HIP events on its launch
+stream during the timed region) and the CPU oracle timed on the host.
 
-Prints one JSON line with the throughput (evals/s), the roofline figures of
-the dominant kernel (timed with HIP events on the launch stream during the
-timed region) and the CPU oracle timed on the host as a reported baseline.
+"batched": 512 problems, n ~ U{16..256}, r ~ U{2..32}, p = 250 r, d in
+{3, 4}, sigma in {1e-3, 1e-2}, 4 randomized-range-finder restarts each, fp32,
+solved together by symtd_solve_batched; solves/s against the plain loop of
+symtd_solve calls on a sample of the same problems, with the final relative
+errors of both.
+
+"served": Poisson arrivals (200 requests/s) of problems drawn the same way to
+a symtd_server; p50/p99 latency (arrival to result) and solves/s, against
+the plain first-in-first-out loop of symtd_solve calls replaying the same
+arrival trace.
 
     python bench.py [--steps K] [--warmup W] [--prec fp32|fp64] [--no-cpu-baseline]
+                    [--only-fg] [--batched N] [--served N]
 """
 
 from __future__ import annotations
@@ -73,6 +84,11 @@ def parse():
     ap.add_argument("--serial", action="store_true", help="model terms on the caller's stream")
     ap.add_argument("--g1-blocks", type=int, default=0)
     ap.add_argument("--g2-splits", type=int, default=0)
+    ap.add_argument("--only-fg", action="store_true", help="headline only (no batched/served legs)")
+    ap.add_argument("--batched", type=int, default=512, help="problems of the batched leg")
+    ap.add_argument("--loop-sample", type=int, default=32, help="problems the per-problem loop solves")
+    ap.add_argument("--served", type=int, default=600, help="requests of the served leg")
+    ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the served leg (requests/s)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB elementwise copy a few times (HBM counter calibration)")
     return ap.parse_args()
@@ -108,6 +124,112 @@ def cpu_baseline(V64, nu, A64, lam, d, seconds):
     dt = time.perf_counter() - t0
     return {"value": k / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{k} full fp64 evaluations of the same workload on the host ({dt:.1f} s)"}
+
+
+def grouped_problems(count, key, restarts=4):
+    """Problems of the grouped workload (device tensors), and their shapes."""
+    import torch
+
+    import paper_1911_03813_amd as S
+    shapes = synth.batch_shapes(count, key)
+    probs = []
+    for i, s in enumerate(shapes):
+        V, nu, _ = synth.gmm(s["n"], s["r"], s["p"], s["sigma"], key, i)
+        probs.append(dict(V=S.colmajor(torch.from_numpy(V).float()).cuda(), nu=torch.from_numpy(nu).cuda(),
+                          d=s["d"], r=s["r"], restarts=restarts, seed=1000 + i, pgtol=1e-4))
+    return probs
+
+
+def loop_solve(S, ctx, pr):
+    kw = {k: v for k, v in pr.items() if k not in ("V", "nu", "d", "r")}
+    return S.symtd_solve(ctx, pr["V"], pr["nu"], pr["d"], pr["r"], **kw)
+
+
+def batched_leg(S, ctx, count, sample):
+    import torch
+    probs = grouped_problems(count, 4)
+    S.symtd_solve_batched(ctx, probs[:4])              # warm the path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = S.symtd_solve_batched(ctx, probs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    sample = min(sample, count)
+    t0 = time.perf_counter()
+    lo = [loop_solve(S, ctx, pr) for pr in probs[:sample]]
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    rb = np.array([r["rel_err"] for r in res])
+    rl = np.array([r["rel_err"] for r in lo])
+    return {"workload": f"{count} problems n~U{{16..256}} r~U{{2..32}} p=250r d in {{3,4}} sigma in {{1e-3,1e-2}}, "
+                        "4 restarts, fp32", "solves_per_s": count / tb, "restart_solves_per_s": 4 * count / tb,
+            "seconds": tb, "steps": int(res[0]["steps"]),
+            "loop": {"problems": sample, "solves_per_s": sample / tl, "seconds": tl},
+            "speedup_vs_loop": (count / tb) / (sample / tl),
+            "rel_err_median": float(np.median(rb)), "rel_err_median_loop_sample": float(np.median(rl)),
+            "rel_err_median_batched_same_sample": float(np.median(rb[:sample])),
+            "evals_median": float(np.median([r["evals"] for r in res]))}
+
+
+def served_leg(S, ctx, count, rate):
+    import torch
+    probs = grouped_problems(count, 5)
+    arrivals = synth.poisson_arrivals(rate, count, 5)
+    warm = count // 10
+    srv = S.Server(0, torch.float32, memory_bytes=16 << 30)
+    try:
+        sub = {}
+        got = {}
+        t_start = time.perf_counter()
+        for i, pr in enumerate(probs):
+            while True:
+                now = time.perf_counter() - t_start
+                if now >= arrivals[i]:
+                    break
+                for res in srv.poll(64, timeout_ms=0):
+                    got[res["id"]] = res
+                time.sleep(min(0.0005, arrivals[i] - now))
+            sub[srv.submit(**pr)] = i
+        while len(got) < count:
+            for res in srv.poll(256, timeout_ms=100):
+                got[res["id"]] = res
+        stats = srv.stats()
+    finally:
+        srv.close()
+    # latency from the arrival of a request (its submit) to its result, on the server clock
+    lat = np.array([got[k]["t_done"] - got[k]["t_submit"] for k in sorted(sub, key=sub.get)])
+    done_t = np.array([got[k]["t_done"] for k in sorted(sub, key=sub.get)])
+    sub_t = np.array([got[k]["t_submit"] for k in sorted(sub, key=sub.get)])
+    meas = slice(warm, count)
+    span = done_t[meas].max() - sub_t[meas].min()
+    rel = np.array([got[k]["rel_err"] for k in sorted(sub, key=sub.get)])
+    # the plain loop: each request solved alone in arrival order (FIFO), service times measured
+    service = []
+    for pr in probs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = loop_solve(S, ctx, pr)
+        torch.cuda.synchronize()
+        service.append((time.perf_counter() - t0, r["rel_err"]))
+    free_at = 0.0
+    lat_loop = []
+    for a, (sv, _) in zip(arrivals, service):
+        start = max(a, free_at)
+        free_at = start + sv
+        lat_loop.append(free_at - a)
+    lat_loop = np.array(lat_loop)
+    rel_loop = np.array([s[1] for s in service])
+    span_loop = free_at - arrivals[warm]
+    return {"workload": f"{count} requests, Poisson {rate:g}/s, problems as the batched leg, 4 restarts, fp32 "
+                        f"(first {warm} excluded)",
+            "p50_ms": 1e3 * float(np.percentile(lat[meas], 50)), "p99_ms": 1e3 * float(np.percentile(lat[meas], 99)),
+            "solves_per_s": (count - warm) / span,
+            "loop": {"p50_ms": 1e3 * float(np.percentile(lat_loop[meas], 50)),
+                     "p99_ms": 1e3 * float(np.percentile(lat_loop[meas], 99)),
+                     "solves_per_s": (count - warm) / span_loop,
+                     "mean_service_ms": 1e3 * float(np.mean([s[0] for s in service]))},
+            "rel_err_median": float(np.median(rel[meas])), "rel_err_median_loop": float(np.median(rel_loop[meas])),
+            "steps": int(stats["steps"])}
 
 
 def main():
@@ -201,6 +323,12 @@ def main():
                      "launches_per_step": per_kernel[dom]["launches"] / args.steps},
         "kernels_us_per_step": {k: round(v["step_us"], 2) for k, v in per_kernel.items()},
     }
+    del Vd, Ad, out
+    if not args.only_fg and args.prec == "fp32":
+        if args.batched > 0:
+            res["batched"] = batched_leg(S, ctx, args.batched, args.loop_sample)
+        if args.served > 0:
+            res["served"] = served_leg(S, ctx, args.served, args.rate)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(Vs, nu, As, lam, d, args.cpu_seconds)
     ctx.close()

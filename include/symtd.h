@@ -197,7 +197,7 @@ typedef struct symtd_solve_result {
   /* caller-owned outputs */
   void* A; int64_t lda;     /* device, n x r of type dt: factors of the best restart */
   double* lambda;           /* device, r values */
-  double* f_restarts;       /* host, `restarts` final f values, or NULL */
+  double* f_restarts;       /* host, `restarts` final f values (working precision), or NULL */
   int64_t* iters_restarts;  /* host, `restarts` values, or NULL */
   int64_t* evals_restarts;  /* host, `restarts` values, or NULL */
   int* exit_restarts;       /* host, `restarts` symtd_exit values, or NULL */
@@ -205,7 +205,9 @@ typedef struct symtd_solve_result {
                                accepted step (NaN past the end), or NULL */
   int64_t trace_len;
   /* written by the call */
-  double f;                 /* final f of the best restart (includes alpha) */
+  double f;                 /* f (alpha included) at the best restart's final point, evaluated
+                               with fp64 products whatever the working precision; the best
+                               restart is the one with the lowest final f in working precision */
   double alpha;             /* the alpha used (0 with SYMTD_ALPHA_NONE) */
   double rel_err;           /* sqrt(max(f, 0) / alpha), NaN without alpha */
   int64_t iters, evals;     /* of the best restart */

@@ -380,7 +380,12 @@ class GroupEngine {
       if (out->evals_restarts) out->evals_restarts[k] = hs[k].evals;
       if (out->exit_restarts) out->exit_restarts[k] = hs[k].reason;
     }
-    out->f = hs[best].f * I->scale;
+    // reported f and relative error: fp64 evaluation at the best final point
+    double f64 = 0.0;
+    symtd_status s = final_fp64<T>(ctx_, st_, I->g.V, I->ld, I->g.nu, I->n, I->p, B.A_t, I->ld, B.lam_t, I->r,
+                                   I->pb.d, I->alpha, &f64);
+    if (s != SYMTD_OK) return s;
+    out->f = f64;
     out->alpha = I->alpha;
     out->rel_err = I->alpha > 0.0 ? std::sqrt(std::max(out->f, 0.0) / I->alpha) : NAN;
     out->iters = hs[best].iters;

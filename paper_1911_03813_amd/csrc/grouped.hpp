@@ -22,7 +22,7 @@
 namespace symtd {
 
 constexpr int GG1_TILE = 256;        // observations per ggemm1 item (4 waves x 4 blocks of 16)
-constexpr int GG2_SPLIT_BLK = 64;    // 16-observation blocks per ggemm2 split (1024 observations)
+constexpr int GG2_SPLIT_BLK = 16;    // 16-observation blocks per ggemm2 split (256 observations)
 constexpr int GG_NT_F32 = 8;         // column subtiles per item (fp32)
 constexpr int GG_NT_F64 = 4;         // column subtiles per item (fp64)
 

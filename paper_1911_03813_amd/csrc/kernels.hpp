@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace symtd {
 
 // Column subtiles handled by one launch of gemm1/gemm2 (16 columns each);
@@ -137,6 +139,9 @@ void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<float>& a);
 void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<double>& a);
 void launch_final_s(dim3 grid, hipStream_t st, const FinalSArgs& a);
 void launch_final_f(dim3 grid, hipStream_t st, const FinalSArgs& a);
+
+void launch_widen(hipStream_t st, const float* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                  int64_t cols);
 
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<float>& a);
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<double>& a);

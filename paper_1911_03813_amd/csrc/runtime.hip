@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -302,6 +303,57 @@ template symtd_status run_rrf<float>(symtd_ctx*, hipStream_t, const float*, int6
 template symtd_status run_rrf<double>(symtd_ctx*, hipStream_t, const double*, int64_t, int64_t, int64_t, int64_t,
                                       int, uint64_t, const LbLane<double>*);
 
+template <typename T>
+symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
+                        int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d, double alpha,
+                        double* f_out) {
+  // scratch: [V64 n x p][A64 n x r][G64 n x r][g r][f 1]
+  auto plan = [&](Carve& c, double** V64, double** A64, double** G64, double** g, double** f) {
+    *V64 = std::is_same<T, float>::value ? c.take<double>((size_t)n * p) : nullptr;
+    *A64 = std::is_same<T, float>::value ? c.take<double>((size_t)n * r) : nullptr;
+    *G64 = c.take<double>((size_t)n * r);
+    *g = c.take<double>((size_t)r);
+    *f = c.take<double>(1);
+  };
+  double *V64, *A64, *G64, *g, *fd;
+  Carve probe((void*)256);
+  plan(probe, &V64, &A64, &G64, &g, &fd);
+  const size_t need = probe.off + 512;
+  hipError_t e;
+  if (need > ctx->wide_bytes) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return ctx->hip_fail(e, "hipDeviceSynchronize");
+    if (ctx->wide) (void)hipFree(ctx->wide);
+    ctx->wide = nullptr;
+    ctx->wide_bytes = 0;
+    if ((e = hipMalloc(&ctx->wide, need)) != hipSuccess) {
+      (void)hipGetLastError();
+      return ctx->fail(SYMTD_ENOMEM, "hipMalloc(%zu) for the fp64 evaluation failed", need);
+    }
+    ctx->wide_bytes = need;
+  }
+  Carve c(ctx->wide);
+  plan(c, &V64, &A64, &G64, &g, &fd);
+  symtd_status s;
+  if constexpr (std::is_same<T, float>::value) {
+    launch_widen(st, V, ldv, V64, n, n, p);
+    launch_widen(st, A, lda, A64, n, n, r);
+    s = run_fg<double>(ctx, st, V64, n, nu, n, p, A64, n, lambda, r, 1, d, alpha, fd, g, G64, n);
+  } else {
+    s = run_fg<double>(ctx, st, V, ldv, nu, n, p, A, lda, lambda, r, 1, d, alpha, fd, g, G64, n);
+  }
+  if (s != SYMTD_OK) return s;
+  if ((e = hipMemcpyAsync(&ctx->fwide_host, fd, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return ctx->hip_fail(e, "final fp64 evaluation");
+  *f_out = ctx->fwide_host;
+  return SYMTD_OK;
+}
+
+template symtd_status final_fp64<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t, int64_t,
+                                        const float*, int64_t, const double*, int64_t, int, double, double*);
+template symtd_status final_fp64<double>(symtd_ctx*, hipStream_t, const double*, int64_t, const double*, int64_t,
+                                         int64_t, const double*, int64_t, const double*, int64_t, int, double, double*);
+
 template <typename S>
 symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, const double* nu,
                        int64_t n, int64_t p, int d, double* alpha) {
@@ -414,6 +466,7 @@ void symtd_destroy(symtd_ctx* ctx) {
   if (ctx->flags) (void)hipFree(ctx->flags);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->sws) (void)hipFree(ctx->sws);
+  if (ctx->wide) (void)hipFree(ctx->wide);
   if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
   delete ctx;
 }

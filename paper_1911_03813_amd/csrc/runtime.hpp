@@ -16,7 +16,10 @@ struct symtd_ctx {
   size_t ws_bytes = 0;
   void* sws = nullptr;  // device workspace of the solver state, grown on demand
   size_t sws_bytes = 0;
+  void* wide = nullptr; // device scratch of the final fp64 evaluation, grown on demand
+  size_t wide_bytes = 0;
   int* host_flag = nullptr;   // pinned host word for polling the solver's stop count
+  double fwide_host = 0.0;    // host landing of the final fp64 evaluation
   // side stream for the model terms, and the events of the fork/join
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_model = nullptr, ev_g1 = nullptr, ev_side = nullptr;
@@ -62,6 +65,14 @@ template <typename T> struct LbLane;
 template <typename T>
 symtd_status run_rrf(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, int64_t n, int64_t p, int64_t r,
                      int restarts, uint64_t seed, const LbLane<T>* lanes_dev);
+
+// f at (lambda, A) evaluated with fp64 products (the stored values of V and A
+// widened exactly when T is float), for the relative error of a finished
+// solve.  Synchronises `st`; returns f in *f_out.
+template <typename T>
+symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
+                        int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d, double alpha,
+                        double* f_out);
 
 // argument checks of a solve request (problem, options, result buffers)
 symtd_status check_solve(symtd_ctx* ctx, const symtd_problem* pb, const symtd_solve_opts* o,

@@ -224,7 +224,11 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
     if (out->evals_restarts) out->evals_restarts[k] = hs[k].evals;
     if (out->exit_restarts) out->exit_restarts[k] = hs[k].reason;
   }
-  out->f = hs[best].f * scale;
+  // the reported f and relative error come from an fp64 evaluation at the
+  // best restart's final point (the working precision may be fp32)
+  double f64 = 0.0;
+  if ((s = final_fp64<T>(ctx, st, V, pb.ldv, pb.nu, n, p, B.A_t, n, B.lam_t, r, d, alpha, &f64)) != SYMTD_OK) return s;
+  out->f = f64;
   out->alpha = alpha;
   out->rel_err = alpha > 0.0 ? std::sqrt(std::max(out->f, 0.0) / alpha) : NAN;
   out->iters = hs[best].iters;

@@ -144,5 +144,6 @@ def test_solve_batched_fp32_mix(ctx):
         print(f"problem {i} n={V.shape[0]} r={r} d={d}: rel_err={out['rel_err']:.3e} "
               f"iters={out['iters']} {S.EXIT_NAMES[out['exit_reason']]}", flush=True)
         assert out["exit_reason"] in (1, 2, 3, 5)
-        assert abs(f_chk - out["f"]) <= 10 * TOL["f32"] * alpha
+        # the reported f is the fp64 evaluation at the returned (fp32) model
+        assert abs(f_chk - out["f"]) <= 1e-11 * alpha
         assert out["best_restart"] == int(np.argmin(out["f_restarts"]))

@@ -205,10 +205,15 @@ def test_best_of_restarts(ctx, kind):
     out = S.symtd_solve(ctx, Vd, nud, d, r, restarts=R, seed=9, init=S.INIT_GAUSS, pgtol=1e-6, max_iters=150)
     fr = out["f_restarts"]
     assert out["best_restart"] == int(np.argmin(fr))
-    assert out["f"] == fr.min()
+    # the reported f is an fp64 evaluation at the best restart's final point:
+    # in fp64 the same value the solve ended with, in fp32 within its tolerance
+    if kind == "f64":
+        assert out["f"] == fr.min()
+    else:
+        assert abs(out["f"] - fr.min()) <= 10 * TOL[kind] * out["alpha"]
     A = out["A"].cpu().numpy().astype(np.float64)
     f_chk = fg_implicit(V, nu, A, out["lam"].cpu().numpy(), d, out["alpha"], with_intermediates=False).f
-    assert abs(f_chk - out["f"]) <= 10 * TOL[kind] * out["alpha"]
+    assert abs(f_chk - out["f"]) <= 1e-11 * out["alpha"]
 
 
 def test_solve_bad_arguments(ctx):

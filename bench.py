@@ -50,9 +50,9 @@ PEAK_HBM_GBS = 8000.0
 # and are reported as null once those sources change.
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
                    "paper_1911_03813_amd/csrc/kcommon.hpp")
-TRAFFIC_SHA = "857cbde6129424ac"
-TRAFFIC_BYTES = {("fp32", "gemm1"): 492.3e6, ("fp32", "gemm2"): 474.4e6,
-                 ("fp64", "gemm1"): 1796.9e6, ("fp64", "gemm2"): 1748.6e6}
+TRAFFIC_SHA = "75e213583d827026"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 492.1e6, ("fp32", "gemm2"): 474.4e6,
+                 ("fp64", "gemm1"): 1796.3e6, ("fp64", "gemm2"): 1748.7e6}
 
 
 def traffic_for(prec, kernel):

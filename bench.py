@@ -41,7 +41,7 @@ import synth  # noqa: E402
 
 WORKLOAD = dict(d=3, n=1000, r=100, p=100_000, sigma=1e-2)
 # MI355X published dense matrix-core peaks (TFLOP/s) and HBM bandwidth (GB/s)
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "fp16": 2500.0}
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per evaluation (summed over the launches of one evaluation) of the
 # two products, from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE (x 1.000)
@@ -143,6 +143,77 @@ def grouped_problems(count, key, restarts=4):
 def loop_solve(S, ctx, pr):
     kw = {k: v for k, v in pr.items() if k not in ("V", "nu", "d", "r")}
     return S.symtd_solve(ctx, pr["V"], pr["nu"], pr["d"], pr["r"], **kw)
+
+
+def precision_leg(S, ctx, Vs, nu, As, lam, d, steps, warmup):
+    """evals/s, product times and error against the fp64 products of every
+    product precision on the large workload (fp32 storage for fp32 / fp16 /
+    bf16x3; the fp64 products evaluate the same stored values widened)."""
+    import torch
+    n, p = Vs.shape
+    r = As.shape[1]
+    flop_gemm = 2.0 * n * p * r
+    out = {}
+    ref = None
+    for name, prec, dt in (("fp64", S.PREC_FP64, torch.float64), ("fp32", S.PREC_FP32, torch.float32),
+                           ("fp16", S.PREC_FP16, torch.float32), ("bf16x3", S.PREC_BF16X3, torch.float32)):
+        Vd = S.colmajor(torch.from_numpy(np.ascontiguousarray(Vs)).to(dt)).cuda()
+        Ad = S.colmajor(torch.from_numpy(np.ascontiguousarray(As)).to(dt)).cuda()
+        nud = torch.from_numpy(nu).cuda()
+        lamd = torch.from_numpy(lam).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        data = S.Data(ctx, Vd, nud, prec)
+        torch.cuda.synchronize()
+        conv = time.perf_counter() - t0
+        res = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty(r, dtype=torch.float64, device="cuda"),
+               S.colmajor(torch.empty(n, r, dtype=dt, device="cuda")))
+        for _ in range(warmup):
+            data.fg(Ad, lamd, d, 0.0, out=res)
+        torch.cuda.synchronize()
+        S.symtd_profile_reset(ctx)
+        S.symtd_profile_enable(ctx, True)
+        k = steps if name != "fp64" else max(10, steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            data.fg(Ad, lamd, d, 0.0, out=res)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / k
+        S.symtd_profile_enable(ctx, False)
+        kus = {}
+        for i, kn in enumerate(S.profile_names()):
+            ms, cnt = S.symtd_profile_read(ctx, i)
+            if cnt:
+                kus[kn] = 1e3 * ms / k
+        S.symtd_profile_reset(ctx)
+        fv = float(res[0].cpu()[0])
+        gv = res[1].cpu().numpy()
+        Gv = res[2].cpu().numpy().astype(np.float64)
+        if ref is None:
+            ref = (fv, gv, Gv)
+        g1 = kus.get("gemm1", float("nan"))
+        entry = {"evals_per_s": 1.0 / sec, "ms_per_eval": 1e3 * sec,
+                 "kernels_us_per_eval": {kk: round(v, 2) for kk, v in kus.items()}}
+        if name != "fp64":
+            # norm-wise relative errors against the fp64 products on the same stored inputs
+            entry["error_vs_fp64"] = {"f": abs(fv - ref[0]) / abs(ref[0]),
+                                      "g_lambda": float(np.max(np.abs(gv - ref[1])) / np.max(np.abs(ref[1]))),
+                                      "G_A": float(np.linalg.norm(Gv - ref[2]) / np.linalg.norm(ref[2])),
+                                      "stated_bound": S.prec_bound(prec, d)}
+        if name in ("fp64", "fp32"):
+            entry["gemm1_mfma_frac"] = flop_gemm / (g1 * 1e-6) / (PEAK_TFLOPS[name] * 1e12)
+        else:
+            mult = 3.0 if name == "bf16x3" else 1.0
+            vbytes = n * p * (4 if name == "bf16x3" else 2)
+            entry["conversion_s"] = conv
+            entry["gemm1_mfma_frac"] = mult * flop_gemm / (g1 * 1e-6) / (PEAK_TFLOPS["fp16"] * 1e12)
+            entry["gemm1_hbm_GBs"] = vbytes / (g1 * 1e-6) / 1e9
+            entry["gemm1_hbm_frac"] = vbytes / (g1 * 1e-6) / (PEAK_HBM_GBS * 1e9)
+            entry["mfma_flop_per_product"] = "3 x 2npr (hi hi, hi lo, lo hi)" if name == "bf16x3" else "2npr"
+        data.close()
+        del Vd, Ad, res
+        out[name] = entry
+    return out
 
 
 def batched_leg(S, ctx, count, sample):
@@ -325,6 +396,7 @@ def main():
     }
     del Vd, Ad, out
     if not args.only_fg and args.prec == "fp32":
+        res["precisions"] = precision_leg(S, ctx, Vs, nu, As, lam, d, args.steps, args.warmup)
         if args.batched > 0:
             res["batched"] = batched_leg(S, ctx, args.batched, args.loop_sample)
         if args.served > 0:

@@ -48,9 +48,19 @@ typedef enum symtd_dtype { SYMTD_F64 = 0, SYMTD_F32 = 1 } symtd_dtype;
 /* Arithmetic used for the two products V'A and V*W of eq. (Y).
  *   SYMTD_PREC_FP64: fp64 matrix-core products (needs SYMTD_F64 storage).
  *   SYMTD_PREC_FP32: fp32 matrix-core products (needs SYMTD_F32 storage).
+ *   SYMTD_PREC_FP16: fp16 operands (V, A and W = nu z^{d-1}, the latter times a
+ *                    power of two that keeps it in fp16's normal range), fp32
+ *                    accumulation; through a data handle (symtd_data_create).
+ *   SYMTD_PREC_BF16X3: every operand split as hi + lo with hi = bf16(x),
+ *                    lo = bf16(x - hi); products hi hi + hi lo + lo hi with fp32
+ *                    accumulation; through a data handle.
  * In every precision the column sums w_j, the split reductions, B = A'A,
- * u, f and g_lambda are accumulated in fp64. */
-typedef enum symtd_prec { SYMTD_PREC_FP64 = 0, SYMTD_PREC_FP32 = 1 } symtd_prec;
+ * u, f and g_lambda are accumulated in fp64.  Stated bounds (errors relative
+ * to the cancelling terms, d = 3): fp64 1e-12, fp32 1e-5, bf16x3
+ * 2 (d+1) 3 2^-16 = 3.7e-4, fp16 2 (d+1) 2 2^-11 = 7.8e-3. */
+typedef enum symtd_prec {
+  SYMTD_PREC_FP64 = 0, SYMTD_PREC_FP32 = 1, SYMTD_PREC_FP16 = 2, SYMTD_PREC_BF16X3 = 3
+} symtd_prec;
 
 typedef struct symtd_ctx symtd_ctx;
 
@@ -96,6 +106,24 @@ symtd_status symtd_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt,
                       const void* A, int64_t lda, const double* lambda, int64_t r, int d,
                       double alpha, symtd_prec prec,
                       double* f, double* g_lambda, void* G_A, int64_t ldg);
+
+/*
+ * Data handles: a data set (V, nu) prepared once for repeated evaluations.
+ * For SYMTD_PREC_FP16 and SYMTD_PREC_BF16X3 (fp32 storage) the handle holds
+ * 16-bit copies of V in two layouts (covariate-contiguous for V'A,
+ * observation-contiguous for V W), converted on `stream`; the call returns
+ * after the conversion.  For SYMTD_PREC_FP32 / FP64 it only records the
+ * pointers.  The caller must keep V and nu unchanged while the handle lives
+ * (nu is read at every evaluation).  symtd_fg_data is symtd_fg on the
+ * handle's data with the handle's precision; A and G_A have the storage type.
+ */
+typedef struct symtd_data symtd_data;
+symtd_status symtd_data_create(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
+                               const double* nu, int64_t n, int64_t p, symtd_prec prec, symtd_data** out);
+void symtd_data_destroy(symtd_data* data);
+symtd_status symtd_fg_data(symtd_ctx* ctx, void* stream, const symtd_data* data, const void* A, int64_t lda,
+                           const double* lambda, int64_t r, int d, double alpha, double* f, double* g_lambda,
+                           void* G_A, int64_t ldg);
 
 /*
  * Algorithm 2 for several models sharing one data tensor: model m (0 <= m <

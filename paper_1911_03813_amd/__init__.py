@@ -23,7 +23,15 @@ SYMTD_OK = 0
 STATUS = {0: "SYMTD_OK", -1: "SYMTD_EINVAL", -2: "SYMTD_EALIGN", -3: "SYMTD_ENOMEM",
           -4: "SYMTD_EDEVICE", -5: "SYMTD_EUNSUPPORTED", -6: "SYMTD_ENONFINITE", -7: "SYMTD_EREJECTED"}
 F64, F32 = 0, 1
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_FP16, PREC_BF16X3 = 0, 1, 2, 3
+
+
+def prec_bound(prec: int, d: int) -> float:
+    """The stated error bound of a product precision (relative to the
+    cancelling terms): fp64 1e-12, fp32 1e-5, bf16x3 2(d+1) 3 2^-16, fp16
+    2(d+1) 2 2^-11."""
+    return {PREC_FP64: 1e-12, PREC_FP32: 1e-5, PREC_BF16X3: 2 * (d + 1) * 3 * 2.0**-16,
+            PREC_FP16: 2 * (d + 1) * 2 * 2.0**-11}[prec]
 
 
 class SymtdError(RuntimeError):
@@ -109,6 +117,9 @@ SIGNATURES = {
                               _dbl, _int, _vp, _vp, _vp, _i64]),
     "symtd_normX": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _vp]),
     "symtd_set_tuning": (_int, [_vp, _int, _i64]),
+    "symtd_data_create": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _c.POINTER(_vp)]),
+    "symtd_data_destroy": (None, [_vp]),
+    "symtd_fg_data": (_int, [_vp, _vp, _vp, _vp, _i64, _vp, _i64, _int, _dbl, _vp, _vp, _vp, _i64]),
     "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
     "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
     "symtd_fg_batched": (_int, [_vp, _vp, _int, _int, _i64, _c.POINTER(FgItem)]),
@@ -480,6 +491,53 @@ class Server:
     def close(self):
         if getattr(self, "_h", None):
             lib().symtd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Data:
+    """A prepared data set (symtd_data_create): V, nu and the product precision.
+
+    fg(A, lam, d, alpha) evaluates f, g_lambda, G_A on it (symtd_fg_data).
+    The tensors V and nu are kept referenced while the handle lives.
+    """
+
+    def __init__(self, ctx: Context, V, nu, prec: int, stream=None):
+        Vp, ldv = _mat(V, "V")
+        n, p = V.shape
+        nup = _vec(nu, "nu", p)
+        h = _vp()
+        _check(ctx, lib().symtd_data_create(ctx.handle, _stream(stream), _dt(V), Vp, ldv, nup, n, p, int(prec),
+                                            ctypes.byref(h)))
+        self._h = h
+        self.ctx, self.V, self.nu, self.prec, self.n, self.p = ctx, V, nu, prec, n, p
+
+    def fg(self, A, lam, d: int, alpha: float = 0.0, out=None, stream=None):
+        import torch
+        Ap, lda = _mat(A, "A", self.V.dtype)
+        n2, r = A.shape
+        if n2 != self.n:
+            raise ValueError("A must have as many rows as V")
+        lp = _vec(lam, "lambda", r)
+        if out is None:
+            f = torch.empty(1, dtype=torch.float64, device=A.device)
+            g = torch.empty(r, dtype=torch.float64, device=A.device)
+            G = colmajor(torch.empty(self.n, r, dtype=A.dtype, device=A.device))
+        else:
+            f, g, G = out
+        Gp, ldg = _mat(G, "G_A", self.V.dtype)
+        _check(self.ctx, lib().symtd_fg_data(self.ctx.handle, _stream(stream), self._h, Ap, lda, lp, r, int(d),
+                                             float(alpha), _vec(f, "f", 1), _vec(g, "g_lambda", r), Gp, ldg))
+        return f, g, G
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().symtd_data_destroy(self._h)
             self._h = None
 
     def __del__(self):

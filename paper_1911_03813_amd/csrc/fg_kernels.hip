@@ -636,7 +636,7 @@ __global__ __launch_bounds__(256) void k_final_G(FinalGArgs<T> a) {
     y += (y0 + y1) + (y2 + y3);
   }
   for (; s < a.nsplit; ++s) y += (double)yp[s * stride];
-  const double gval = -2.0 * a.d * (y - a.YM[(int64_t)j * a.n + i]) * a.lambda[j];
+  const double gval = -2.0 * a.d * (a.yscale * y - a.YM[(int64_t)j * a.n + i]) * a.lambda[j];
   a.G[(int64_t)j * a.ldg + i] = (T)gval;
 }
 

@@ -103,6 +103,7 @@ struct FinalGArgs {
   const double* YM; int n; int r; int d;
   const double* lambda;
   T* G; int64_t ldg;
+  double yscale;      // Y = yscale * (sum of the partials)
 };
 
 struct FinalSArgs {

@@ -1,0 +1,496 @@
+// fp16 / bf16x3 products of the evaluation (see lp.hpp).
+//
+// Both products are "k-contiguous" matrix-core products: every operand
+// column holds its k values contiguously, so a lane's MFMA operand (8
+// consecutive k values, 16 bytes) is one vector from LDS.  Chunks of each
+// column move from HBM to LDS as 16-byte pieces by direct global-to-LDS
+// loads (every thread moves the same number of pieces; the piece for LDS slot
+// s is chosen so that it lands on s), two LDS stages alternate, and LDS slots
+// are XOR-swizzled so that the 16 columns of a fragment read hit distinct
+// banks.  The MFMA is v_mfma_f32_16x16x32_{f16,bf16}: lane 16 g + c supplies
+// row c and k values 8 g .. 8 g + 7 of a 32-deep step, and holds output rows
+// 4 g .. 4 g + 3 of column c.
+#include <type_traits>
+
+#include "kcommon.hpp"
+#include "lp.hpp"
+
+namespace symtd {
+
+namespace {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+template <int KIND> struct LpT;
+template <> struct LpT<LP_F16> {
+  using E = _Float16;
+  static constexpr int PLANES = 1;
+  static __device__ __forceinline__ f4 mac(const u4* v, const u4* a, f4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, v[0]), __builtin_bit_cast(h8, a[0]), acc,
+                                                  0, 0, 0);
+  }
+  static __device__ __forceinline__ void split(double x, E* out) { out[0] = (E)(float)x; }
+};
+template <> struct LpT<LP_BF16X3> {
+  using E = __bf16;
+  static constexpr int PLANES = 2;
+  // (hi, lo) x (hi, lo) without the lo lo term
+  static __device__ __forceinline__ f4 mac(const u4* v, const u4* a, f4 acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, v[1]), __builtin_bit_cast(b8, a[0]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, v[0]), __builtin_bit_cast(b8, a[1]), acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, v[0]), __builtin_bit_cast(b8, a[0]), acc, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void split(double x, E* out) {
+    const float xf = (float)x;
+    const __bf16 hi = (__bf16)xf;
+    out[0] = hi;
+    out[1] = (__bf16)(float)(x - (double)(float)hi);
+  }
+};
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// One chunk's LDS stage: V/X part then A/W part, 16-byte units.
+template <int KIND, int NT>
+struct LpStage {
+  static constexpr int PL = LpT<KIND>::PLANES;
+  static constexpr int U = lp_chunk(KIND) / 8;                 // units per column per plane
+  static constexpr int XU = PL * LP_SLAB * U;                   // units of the slab operand
+  static constexpr int YU = PL * 16 * NT * U;                   // units of the column operand
+  static constexpr int XP = (XU + 255) / 256;                   // pieces per thread
+  static constexpr int YP = (YU + 255) / 256;
+  static constexpr int DPC = XP + YP;
+  static __device__ __forceinline__ int swz(int col, int q) { return col * U + (q ^ ((col >> 1) & (U - 1))); }
+  static __device__ __forceinline__ void unswz(int s, int& col, int& q) {
+    col = s / U;
+    q = (s % U) ^ ((col >> 1) & (U - 1));
+  }
+};
+
+// DMA of chunk kc: slab operand rows xcol(col) (plane stride xplane) and
+// column operand columns ycol(col); k offset k0 (elements)
+template <int KIND, int NT, typename XF, typename YF>
+__device__ __forceinline__ void lp_dma(u4* lx, u4* ly, int tid, int wave, XF xsrc, YF ysrc) {
+  using S = LpStage<KIND, NT>;
+#pragma unroll
+  for (int i = 0; i < S::XP; ++i) {
+    const int P = tid + 256 * i;
+    const void* src = xsrc(0, 0, 0);                             // padding pieces: any valid address
+    if (P < S::XU) {
+      const int pl = P / (LP_SLAB * S::U);
+      int col, q;
+      S::unswz(P % (LP_SLAB * S::U), col, q);
+      src = xsrc(pl, col, q);
+    }
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)((char*)lx + 16 * (256 * i + 64 * wave)),
+                                     16, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < S::YP; ++i) {
+    const int P = tid + 256 * i;
+    const void* src = ysrc(0, 0, 0);
+    if (P < S::YU) {
+      const int pl = P / (16 * NT * S::U);
+      int col, q;
+      S::unswz(P % (16 * NT * S::U), col, q);
+      src = ysrc(pl, col, q);
+    }
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)((char*)ly + 16 * (256 * i + 64 * wave)),
+                                     16, 0, 0);
+  }
+}
+
+// multiply one chunk held in LDS into acc (fragments double-buffered)
+template <int KIND, int NT>
+__device__ __forceinline__ void lp_compute(const u4* lx, const u4* ly, int wave, int g, int c, f4 (&acc)[LP_MT][NT]) {
+  using S = LpStage<KIND, NT>;
+  constexpr int PL = S::PL;
+  constexpr int J = S::U / 4;
+  u4 fv[2][LP_MT][PL], fa[2][NT][PL];
+  auto frag = [&](int b, int jg) {
+    const int q = 4 * jg + g;
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) fv[b][m][pl] = lx[pl * LP_SLAB * S::U + S::swz(16 * (LP_MT * wave + m) + c, q)];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) fa[b][t][pl] = ly[pl * 16 * NT * S::U + S::swz(16 * t + c, q)];
+  };
+  frag(0, 0);
+#pragma unroll
+  for (int jg = 0; jg < J; ++jg) {
+    if (jg + 1 < J) frag((jg + 1) & 1, jg + 1);
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = LpT<KIND>::mac(fv[jg & 1][m], fa[jg & 1][t], acc[m][t]);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// gemm1: Z = Vc' Ac for one column group, stream-K over (slab, chunk) as in
+// the fp32 kernel; epilogue W = 2^s nu z^{d-1} (column-major, ld ldr) and
+// fp64 column sums of nu z^d, one row per wave.
+// ---------------------------------------------------------------------------
+template <int KIND, int NT>
+__global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
+  using S = LpStage<KIND, NT>;
+  using E = typename LpT<KIND>::E;
+  constexpr int PL = S::PL;
+  constexpr int KCH = lp_chunk(KIND);
+  constexpr int PART = LP_WAVES * LP_MT * NT * 256;
+  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256];
+  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t B = a.nblocks, blk = blockIdx.x;
+  const int64_t KC = a.ldc / KCH;
+  const int64_t U = (int64_t)a.nslab * KC;
+  const int64_t u0 = blk * U / B, u1 = (blk + 1) * U / B;
+  const E* V = (const E*)a.Vc;
+  const E* Ac = (const E*)a.Ac;
+  const int dm1 = a.d - 1;
+
+  f4 acc[LP_MT][NT];
+#pragma unroll
+  for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
+  double wsum[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) wsum[t] = 0.0;
+
+  auto dma = [&](u4* lx, u4* ly, int64_t sl, int64_t kc) {
+    const int64_t k0 = kc * KCH;
+    auto xs = [&](int pl, int col, int q) -> const void* {
+      int64_t l = (int64_t)LP_SLAB * sl + col;
+      l = l < a.p ? l : (int64_t)a.p - 1;                        // columns past p: weight 0
+      return V + pl * a.vplane + l * a.ldc + k0 + 8 * q;
+    };
+    auto ys = [&](int pl, int col, int q) -> const void* {
+      return Ac + pl * a.aplane + (int64_t)(a.col0 + col) * a.ldc + k0 + 8 * q;
+    };
+    lp_dma<KIND, NT>(lx, ly, tid, wave, xs, ys);
+  };
+  auto arrive = [&]() {
+    wait_vm<0>();
+    __syncthreads();
+  };
+
+  if (u0 < u1) {
+    int64_t sl = u0 / KC, kb = u0 - sl * KC;
+    const int64_t sl_last = (u1 - 1) / KC;
+    while (true) {
+      const int64_t ke = (sl == sl_last) ? u1 - sl * KC : KC;
+      const int64_t nk = ke - kb;
+      dma(lx0, ly0, sl, kb);
+      int64_t q = 0;
+      for (; q + 2 <= nk; q += 2) {
+        arrive();
+        dma(lx1, ly1, sl, kb + q + 1);
+        lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
+        arrive();
+        if (q + 2 < nk) dma(lx0, ly0, sl, kb + q + 2);
+        lp_compute<KIND, NT>(lx1, ly1, wave, g, c, acc);
+      }
+      if (q < nk) {
+        arrive();
+        lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
+      }
+      __syncthreads();   // every stage is read before the next slab overwrites it
+
+      if (kb > 0) {
+        // not the owner: publish this block's partial for the previous block
+        float* pp = a.part + blk * PART + (int64_t)wave * (LP_MT * NT * 256);
+#pragma unroll
+        for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            *reinterpret_cast<f4*>(pp + ((m * NT + t) * 64 + lane) * 4) = acc[m][t];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (ke < KC) {
+          int spins = 0;
+          while (__builtin_amdgcn_readfirstlane(
+                     __hip_atomic_load(a.flag + blk + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1 << 24)) {
+              __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+          const float* pp = a.part + (blk + 1) * PART + (int64_t)wave * (LP_MT * NT * 256);
+#pragma unroll
+          for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] += *reinterpret_cast<const f4*>(pp + ((m * NT + t) * 64 + lane) * 4);
+          __syncthreads();
+          if (tid == 0) __hip_atomic_store(a.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // epilogue: acc[m][t][v] = z at l = 16 b + 4 g + v, column col0 + 16 t + c
+#pragma unroll
+        for (int m = 0; m < LP_MT; ++m) {
+          const int64_t lb = (int64_t)LP_SLAB * sl + 16 * (LP_MT * wave + m) + 4 * g;
+          double nl[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) nl[v] = (lb + v < a.p) ? a.nu[lb + v] : 0.0;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            E out[PL][4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const double z = (double)acc[m][t][v];
+              const double wv = nl[v] * ipow(z, dm1);
+              wsum[t] += wv * z;
+              E parts[PL];
+              LpT<KIND>::split(a.wscale * wv, parts);
+#pragma unroll
+              for (int pl = 0; pl < PL; ++pl) out[pl][v] = parts[pl];
+            }
+            const int64_t col = a.col0 + 16 * t + c;
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl) {
+              E* dst = (E*)a.W + pl * a.wplane + col * a.ldr + lb;
+              uint2 packed;
+              __builtin_memcpy(&packed, out[pl], sizeof(packed));
+              *reinterpret_cast<uint2*>(dst) = packed;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
+      if (sl == sl_last) break;
+      ++sl;
+      kb = 0;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    double s = wsum[t];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (g == 0) a.wpart[(blk * LP_WAVES + wave) * (int64_t)a.rp + a.col0 + 16 * t + c] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gemm2: partial Y = Vr W over one split of the observations, one block per
+// (row slab, split); rows past n are computed from a clamped row and not read
+// ---------------------------------------------------------------------------
+template <int KIND, int NT>
+__global__ __launch_bounds__(256) void k_lp_gemm2(LpG2Args a) {
+  using S = LpStage<KIND, NT>;
+  using E = typename LpT<KIND>::E;
+  constexpr int KCH = lp_chunk(KIND);
+  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256];
+  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  const int slab = blockIdx.x % a.nslab, split = blockIdx.x / a.nslab;
+  const int64_t KC = a.ldr / KCH;
+  const int64_t kb = (int64_t)split * a.chunks_per_split;
+  const int64_t ke = min(KC, kb + a.chunks_per_split);
+  const E* Vr = (const E*)a.Vr;
+  const E* W = (const E*)a.W;
+  f4 acc[LP_MT][NT];
+#pragma unroll
+  for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
+  auto dma = [&](u4* lx, u4* ly, int64_t kc) {
+    const int64_t k0 = kc * KCH;
+    auto xs = [&](int pl, int col, int q) -> const void* {
+      int64_t i = (int64_t)LP_SLAB * slab + col;
+      i = i < a.n ? i : (int64_t)a.n - 1;
+      return Vr + pl * a.vplane + i * a.ldr + k0 + 8 * q;
+    };
+    auto ys = [&](int pl, int col, int q) -> const void* {
+      return W + pl * a.wplane + (int64_t)(a.col0 + col) * a.ldr + k0 + 8 * q;
+    };
+    lp_dma<KIND, NT>(lx, ly, tid, wave, xs, ys);
+  };
+  auto arrive = [&]() {
+    wait_vm<0>();
+    __syncthreads();
+  };
+  const int64_t nk = ke - kb;
+  if (nk > 0) {
+    dma(lx0, ly0, kb);
+    int64_t q = 0;
+    for (; q + 2 <= nk; q += 2) {
+      arrive();
+      dma(lx1, ly1, kb + q + 1);
+      lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
+      arrive();
+      if (q + 2 < nk) dma(lx0, ly0, kb + q + 2);
+      lp_compute<KIND, NT>(lx1, ly1, wave, g, c, acc);
+    }
+    if (q < nk) {
+      arrive();
+      lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
+    }
+  }
+  // acc[m][t][v] = Y[slab rows + 16 (MT wave + m) + 4 g + v][col0 + 16 t + c]
+#pragma unroll
+  for (int m = 0; m < LP_MT; ++m) {
+    const int64_t row = (int64_t)LP_SLAB * slab + 16 * (LP_MT * wave + m) + 4 * g;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float* col = a.Ypart + ((int64_t)split * a.rp + a.col0 + 16 * t + c) * a.npad;
+      *reinterpret_cast<f4*>(col + row) = acc[m][t];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void k_lp_pack_a(LpPackArgs a) {
+  using E = typename LpT<KIND>::E;
+  constexpr int PL = LpT<KIND>::PLANES;
+  const int64_t total = (int64_t)a.rp * a.ldc;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / a.ldc, k = e - j * a.ldc;
+    const double x = (k < a.n && j < a.r) ? (double)a.A[j * a.lda + k] : 0.0;
+    E parts[PL];
+    LpT<KIND>::split(x, parts);
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) ((E*)a.Ac)[pl * a.aplane + e] = parts[pl];
+  }
+}
+
+// Vc (column-major, ld ldc) elementwise; Vr (row-major, ld ldr) through
+// 32 x 32 LDS tiles so that both sides are read and written in rows
+template <int KIND>
+__global__ __launch_bounds__(256) void k_lp_conv_c(LpConvArgs a) {
+  using E = typename LpT<KIND>::E;
+  constexpr int PL = LpT<KIND>::PLANES;
+  const int64_t total = (int64_t)a.p * a.ldc;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t l = e / a.ldc, k = e - l * a.ldc;
+    const double x = k < a.n ? (double)a.V[l * a.ldv + k] : 0.0;
+    E parts[PL];
+    LpT<KIND>::split(x, parts);
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) ((E*)a.Vc)[pl * a.plane_c + e] = parts[pl];
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_lp_conv_r(LpConvArgs a) {
+  using E = typename LpT<KIND>::E;
+  constexpr int PL = LpT<KIND>::PLANES;
+  __shared__ float tile[32][33];
+  const int64_t l0 = (int64_t)blockIdx.x * 32, i0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t l = l0 + yy, i = i0 + tx;
+    tile[yy][tx] = (l < a.p && i < a.n) ? a.V[l * a.ldv + i] : 0.0f;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t i = i0 + yy, l = l0 + tx;
+    if (i < a.n && l < a.ldr) {
+      E parts[PL];
+      LpT<KIND>::split((double)tile[tx][yy], parts);
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) ((E*)a.Vr)[pl * a.plane_r + i * a.ldr + l] = parts[pl];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_max_abs(const double* x, int64_t count, double* out) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) m = fmax(m, fabs(x[i]));
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+template <int KIND>
+void g1(int nt, dim3 grid, hipStream_t st, const LpG1Args& a) {
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((k_lp_gemm1<KIND, 1>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_lp_gemm1<KIND, 2>), grid, dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_lp_gemm1<KIND, 3>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_lp_gemm1<KIND, 4>), grid, dim3(256), 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_lp_gemm1<KIND, 5>), grid, dim3(256), 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_lp_gemm1<KIND, 6>), grid, dim3(256), 0, st, a); break;
+    case 7: hipLaunchKernelGGL((k_lp_gemm1<KIND, 7>), grid, dim3(256), 0, st, a); break;
+    default: break;
+  }
+}
+template <int KIND>
+void g2(int nt, dim3 grid, hipStream_t st, const LpG2Args& a) {
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((k_lp_gemm2<KIND, 1>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_lp_gemm2<KIND, 2>), grid, dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_lp_gemm2<KIND, 3>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_lp_gemm2<KIND, 4>), grid, dim3(256), 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_lp_gemm2<KIND, 5>), grid, dim3(256), 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_lp_gemm2<KIND, 6>), grid, dim3(256), 0, st, a); break;
+    case 7: hipLaunchKernelGGL((k_lp_gemm2<KIND, 7>), grid, dim3(256), 0, st, a); break;
+    default: break;
+  }
+}
+}  // namespace
+
+void launch_lp_gemm1(int kind, int nt, dim3 grid, hipStream_t st, const LpG1Args& a) {
+  if (kind == LP_F16) g1<LP_F16>(nt, grid, st, a);
+  else g1<LP_BF16X3>(nt, grid, st, a);
+}
+void launch_lp_gemm2(int kind, int nt, dim3 grid, hipStream_t st, const LpG2Args& a) {
+  if (kind == LP_F16) g2<LP_F16>(nt, grid, st, a);
+  else g2<LP_BF16X3>(nt, grid, st, a);
+}
+void launch_lp_pack_a(int kind, hipStream_t st, const LpPackArgs& a) {
+  const int64_t total = (int64_t)a.rp * a.ldc;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  if (kind == LP_F16) hipLaunchKernelGGL(k_lp_pack_a<LP_F16>, dim3(blocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_lp_pack_a<LP_BF16X3>, dim3(blocks), dim3(256), 0, st, a);
+}
+void launch_lp_convert(int kind, hipStream_t st, const LpConvArgs& a) {
+  const int64_t total = (int64_t)a.p * a.ldc;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+  const dim3 tgrid((unsigned)((a.ldr + 31) / 32), (unsigned)((a.n + 31) / 32));
+  if (kind == LP_F16) {
+    hipLaunchKernelGGL(k_lp_conv_c<LP_F16>, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_lp_conv_r<LP_F16>, tgrid, dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(k_lp_conv_c<LP_BF16X3>, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_lp_conv_r<LP_BF16X3>, tgrid, dim3(256), 0, st, a);
+  }
+}
+void launch_max_abs(hipStream_t st, const double* x, int64_t count, double* out) {
+  hipLaunchKernelGGL(k_max_abs, dim3(1), dim3(256), 0, st, x, count, out);
+}
+
+}  // namespace symtd

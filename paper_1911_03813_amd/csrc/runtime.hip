@@ -252,7 +252,7 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   }
   (void)hipStreamWaitEvent(st, ctx->ev_model, 0);
   {
-    FinalGArgs<T> ag{Ypart, P.npad, P.rp, P.nsplit, YM, (int)n, (int)r, d, lambda, G, ldg};
+    FinalGArgs<T> ag{Ypart, P.npad, P.rp, P.nsplit, YM, (int)n, (int)r, d, lambda, G, ldg, 1.0};
     const dim3 grid((unsigned)((n + 255) / 256), (unsigned)r);
     ctx->prof_begin(3, st);
     launch_final_G(grid, st, ag);

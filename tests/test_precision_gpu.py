@@ -1,0 +1,85 @@
+"""Parity of the fp16 and bf16x3 product paths (data handles) with the fp64
+oracle, within the stated bounds (errors relative to the cancelling terms,
+oracle.fg.magnitudes): bf16x3 2 (d+1) 3 2^-16, fp16 2 (d+1) 2 2^-11.  The
+oracle evaluates the stored fp32 inputs; the 16-bit rounding of V, A and W is
+part of the path's error.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import compare_fg, gpu_available, make_case, to_dev
+from oracle.normx import normx_implicit
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+
+    import paper_1911_03813_amd as S
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, n, p, r, d, key, prec, sigma=1e-2, alpha=None):
+    V, nu, A, lam = make_case(n, p, r, d, key, sigma, "f32")
+    if alpha is None:
+        alpha = normx_implicit(V, nu, d) if p <= 20000 else 0.0
+    print(f"case n={n} p={p} r={r} d={d} prec={prec}", flush=True)
+    data = S.Data(ctx, to_dev(V, torch.float32), to_dev(nu, torch.float64), prec)
+    f, g, G = data.fg(to_dev(A, torch.float32), to_dev(lam, torch.float64), d, alpha)
+    torch.cuda.synchronize()
+    got = (float(f.cpu()[0]), g.cpu().numpy(), G.cpu().numpy().astype(np.float64))
+    data.close()
+    ef, eg, eG = compare_fg(got, V, nu, A, lam, d, alpha, "f32")
+    bound = S.prec_bound(prec, d)
+    print(f"  errors f={ef:.2e} g={eg:.2e} G={eG:.2e} (bound {bound:.1e})", flush=True)
+    assert ef <= bound and eg <= bound and eG <= bound, (ef, eg, eG, bound)
+    return ef, eg, eG
+
+
+PRECS = ["bf16x3", "fp16"]
+
+
+def prec_of(name):
+    return S.PREC_BF16X3 if name == "bf16x3" else S.PREC_FP16
+
+
+@pytest.mark.parametrize("name", PRECS)
+def test_small_and_mid(ctx, name):
+    run(ctx, 10, 750, 3, 3, (1,), prec_of(name))
+    run(ctx, 100, 5000, 20, 4, (2,), prec_of(name))
+
+
+@pytest.mark.parametrize("n,p,r,d", [
+    (1, 1, 1, 3), (3, 7, 2, 2), (17, 33, 5, 3), (64, 129, 16, 3), (130, 1000, 33, 4),
+    (257, 4099, 7, 3), (96, 3000, 112, 3), (40, 2000, 129, 3), (200, 6000, 100, 3),
+])
+@pytest.mark.parametrize("name", PRECS)
+def test_shape_sweep(ctx, name, n, p, r, d):
+    run(ctx, n, p, r, d, (3, n, p, r, d), prec_of(name))
+
+
+@pytest.mark.parametrize("name", PRECS)
+def test_large(ctx, name):
+    # d=3, n=1000, r=100, p=100000: the large single-instance shape
+    run(ctx, 1000, 100_000, 100, 3, (8,), prec_of(name), alpha=0.0)
+
+
+def test_fp32_handle_forwards(ctx):
+    V, nu, A, lam = make_case(50, 1500, 9, 3, (4,), 1e-2, "f32")
+    Vd, nud = to_dev(V, torch.float32), to_dev(nu, torch.float64)
+    Ad, ld = to_dev(A, torch.float32), to_dev(lam, torch.float64)
+    data = S.Data(ctx, Vd, nud, S.PREC_FP32)
+    a = data.fg(Ad, ld, 3, 0.5)
+    b = S.symtd_fg(ctx, Vd, nud, Ad, ld, 3, 0.5)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    data.close()

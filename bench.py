@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--prec", choices=["fp32", "fp64", "fp16", "bf16x3"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--serial", action="store_true", help="model terms on the caller's stream")
@@ -320,12 +320,13 @@ def main():
 
     W = WORKLOAD
     d, n, r, p = W["d"], W["n"], W["r"], W["p"]
-    dt = torch.float32 if args.prec == "fp32" else torch.float64
+    lowp = args.prec in ("fp16", "bf16x3")
+    dt = torch.float64 if args.prec == "fp64" else torch.float32
     V, nu, _ = synth.gmm(n, r, p, W["sigma"], 3)
     A = synth.gauss_factors(n, r, 3, 5)
     lam = np.ones(r)
-    Vs = V.astype(np.float32).astype(np.float64) if args.prec == "fp32" else V
-    As = A.astype(np.float32).astype(np.float64) if args.prec == "fp32" else A
+    Vs = V if args.prec == "fp64" else V.astype(np.float32).astype(np.float64)
+    As = A if args.prec == "fp64" else A.astype(np.float32).astype(np.float64)
 
     dev = torch.device("cuda:0")
     Vd = S.colmajor(torch.from_numpy(np.ascontiguousarray(Vs)).to(dt)).to(dev)
@@ -338,10 +339,17 @@ def main():
     S.symtd_set_tuning(ctx, S.TUNE_G2_SPLITS, args.g2_splits)
     out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(r, dtype=torch.float64, device=dev),
            S.colmajor(torch.empty(n, r, dtype=dt, device=dev)))
-    stream = torch.cuda.current_stream()
+    # the 16-bit precisions evaluate on a prepared data handle (conversion outside the timed region)
+    data = S.Data(ctx, Vd, nud, S.PREC_FP16 if args.prec == "fp16" else S.PREC_BF16X3) if lowp else None
+
+    def evaluate():
+        if lowp:
+            data.fg(Ad, lamd, d, 0.0, out=out)
+        else:
+            S.symtd_fg(ctx, Vd, nud, Ad, lamd, d, 0.0, out=out)
 
     for _ in range(args.warmup):
-        S.symtd_fg(ctx, Vd, nud, Ad, lamd, d, 0.0, out=out)
+        evaluate()
     torch.cuda.synchronize()
 
     S.symtd_profile_reset(ctx)
@@ -349,7 +357,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        S.symtd_fg(ctx, Vd, nud, Ad, lamd, d, 0.0, out=out)
+        evaluate()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     S.symtd_profile_enable(ctx, False)
@@ -364,13 +372,14 @@ def main():
     evals = 1.0 / sec
     flop_gemm = 2.0 * n * p * r                       # each of the two products
     flop_step = 2 * flop_gemm + 4.0 * n * r * r       # plus B = A'A and A D_lambda C
-    peak = PEAK_TFLOPS[args.prec]
+    peak = PEAK_TFLOPS["fp16" if lowp else args.prec]
+    mult = 3.0 if args.prec == "bf16x3" else 1.0     # executed matrix-core flops per algorithmic flop
     # the dominant product; with r > 16 * (subtiles per launch) it runs as
     # several column-group launches, so its algorithmic flops per step are
     # divided by its summed launch time per step
     dom = max(("gemm1", "gemm2"), key=lambda k: per_kernel.get(k, {"step_us": 0})["step_us"])
     dom_us = per_kernel[dom]["step_us"]
-    achieved = flop_gemm / (dom_us * 1e-6) / 1e12
+    achieved = mult * flop_gemm / (dom_us * 1e-6) / 1e12
     traffic = traffic_for(args.prec, dom)
 
     res = {
@@ -384,16 +393,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16", "bf16x3": "bf16x3"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "large single instance: Gaussian mixture d=3 n=1000 r=100 p=100000 sigma=1e-2",
                    "d": d, "n": n, "r": r, "p": p, "precision": args.prec, "storage": args.prec},
-        "step_mfma_frac": flop_step * evals / (peak * 1e12),
+        "step_mfma_frac": mult * flop_step * evals / (peak * 1e12),
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "launches_per_step": per_kernel[dom]["launches"] / args.steps},
         "kernels_us_per_step": {k: round(v["step_us"], 2) for k, v in per_kernel.items()},
     }
+    if data is not None:
+        data.close()
     del Vd, Ad, out
     if not args.only_fg and args.prec == "fp32":
         res["precisions"] = precision_leg(S, ctx, Vs, nu, As, lam, d, args.steps, args.warmup)

@@ -24,7 +24,7 @@ struct symtd_data {
   int64_t n = 0, p = 0;
   void* Vc = nullptr;            // 16-bit copies (see lp.hpp)
   void* Vr = nullptr;
-  int64_t ldc = 0, ldr = 0, plane_c = 0, plane_r = 0;
+  int64_t ldc = 0, ldr = 0, kc_len = 0, kr_len = 0, plane_c = 0, plane_r = 0;
   double wscale = 1.0;
 };
 
@@ -38,11 +38,11 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
   const int64_t n = D->n, p = D->p;
   const int nt_tot = (int)((r + 15) / 16);
   const int rp = 16 * nt_tot;
-  const int nslab1 = (int)(D->ldr / LP_SLAB);
+  const int nslab1 = (int)(D->kr_len / LP_SLAB);
   const int nblocks1 = std::min(ctx->cu_count, nslab1);
   const int nslab2 = (int)((n + LP_SLAB - 1) / LP_SLAB);
   const int64_t npad = (int64_t)nslab2 * LP_SLAB;
-  const int64_t KC2 = D->ldr / lp_chunk(kind);
+  const int64_t KC2 = D->kr_len / lp_chunk(kind);
   int nsplit = std::max(1, (ctx->cu_count + nslab2 - 1) / nslab2);
   const int cps = (int)((KC2 + nsplit - 1) / nsplit);
   nsplit = (int)((KC2 + cps - 1) / cps);
@@ -52,7 +52,7 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
   auto plan = [&](Carver& c, void** Ac, void** W, double** wpart, float** part, float** Ypart, double** Bpart,
                   double** B, double** C, double** YM, double** fpart) {
     *Ac = c.take<uint16_t>((size_t)PL * D->ldc * rp);
-    *W = c.take<uint16_t>((size_t)PL * D->ldr * rp);
+    *W = c.take<uint16_t>((size_t)PL * D->kr_len * rp);
     *wpart = c.take<double>((size_t)LP_WAVES * nblocks1 * rp);
     *part = c.take<float>((size_t)nblocks1 * LP_WAVES * LP_MT * LP_NT_MAX * 256);
     *Ypart = c.take<float>((size_t)nsplit * rp * npad);
@@ -71,7 +71,7 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
   if (s != SYMTD_OK) return s;
   Carver cv(ctx->ws);
   plan(cv, &Ac, &W, &wpart, &part, &Ypart, &Bpart, &B, &C, &YM, &fpart);
-  const int64_t aplane = D->ldc * rp, wplane = D->ldr * rp;
+  const int64_t aplane = D->ldc * rp, wplane = D->kr_len * rp;
   hipStream_t side = ctx->tune_serial ? st : ctx->side;
 
   (void)hipEventRecord(ctx->ev_fork, st);
@@ -89,13 +89,13 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
     (void)hipEventRecord(ctx->ev_model, side);
   }
   {
-    LpPackArgs pa{A, lda, (int)n, (int)r, Ac, D->ldc, rp, aplane};
+    LpPackArgs pa{A, lda, (int)n, (int)r, Ac, D->ldc, D->kc_len, rp, aplane};
     launch_lp_pack_a(kind, st, pa);
   }
   for (int t0 = 0; t0 < nt_tot; t0 += LP_NT_MAX) {
     const int nt = std::min(LP_NT_MAX, nt_tot - t0);
-    LpG1Args a1{D->Vc, D->ldc, D->plane_c, D->nu, (int)n, (int)p, Ac, aplane, 16 * t0, rp, nslab1, nblocks1, d,
-                D->wscale, W, D->ldr, wplane, wpart, part, ctx->flags, ctx->dev_err};
+    LpG1Args a1{D->Vc, D->ldc, D->kc_len, D->plane_c, D->nu, (int)n, (int)p, Ac, aplane, 16 * t0, rp, nslab1,
+                nblocks1, d, D->wscale, W, D->kr_len, wplane, wpart, part, ctx->flags, ctx->dev_err};
     ctx->prof_begin(0, st);
     launch_lp_gemm1(kind, nt, dim3(nblocks1), st, a1);
     ctx->prof_end(st);
@@ -112,9 +112,9 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
   }
   for (int t0 = 0; t0 < nt_tot; t0 += LP_NT_MAX) {
     const int nt = std::min(LP_NT_MAX, nt_tot - t0);
-    LpG2Args a2{D->Vr, D->ldr, D->plane_r, W, wplane, (int)n, 16 * t0, rp, nslab2, nsplit, cps, Ypart, npad};
+    LpG2Args a2{D->Vr, D->ldr, D->kr_len, D->plane_r, W, wplane, (int)n, 16 * t0, rp, nslab2, nsplit, cps, Ypart, npad};
     ctx->prof_begin(1, st);
-    launch_lp_gemm2(kind, nt, dim3((unsigned)(nslab2 * nsplit)), st, a2);
+    launch_lp_gemm2(kind, nt, dim3((unsigned)(nslab2 * 8 * ((nsplit + 7) / 8))), st, a2);
     ctx->prof_end(st);
   }
   (void)hipStreamWaitEvent(st, ctx->ev_model, 0);
@@ -154,8 +154,10 @@ symtd_status symtd_data_create(symtd_ctx* ctx, void* stream, symtd_dtype dt, con
     hipStream_t st = (hipStream_t)stream;
     D->kind = prec == SYMTD_PREC_FP16 ? LP_F16 : LP_BF16X3;
     const int PL = D->kind == LP_F16 ? 1 : 2;
-    D->ldc = LP_PAD * ((n + LP_PAD - 1) / LP_PAD);
-    D->ldr = LP_PAD * ((p + LP_PAD - 1) / LP_PAD);
+    D->kc_len = LP_PAD * ((n + LP_PAD - 1) / LP_PAD);
+    D->kr_len = LP_PAD * ((p + LP_PAD - 1) / LP_PAD);
+    D->ldc = D->kc_len + LP_SKEW;
+    D->ldr = D->kr_len + LP_SKEW;
     D->plane_c = D->ldc * p;
     D->plane_r = n * D->ldr;
     hipError_t e;
@@ -165,7 +167,8 @@ symtd_status symtd_data_create(symtd_ctx* ctx, void* stream, symtd_dtype dt, con
       symtd_data_destroy(D);
       return ctx->fail(SYMTD_ENOMEM, "device copies of V (%lld x %lld, 16-bit)", (long long)n, (long long)p);
     }
-    LpConvArgs ca{(const float*)V, ldv, (int)n, (int)p, D->Vc, D->ldc, D->Vr, D->ldr, D->plane_c, D->plane_r};
+    LpConvArgs ca{(const float*)V, ldv, (int)n, (int)p, D->Vc, D->ldc, D->kc_len, D->Vr, D->ldr, D->kr_len,
+                  D->plane_c, D->plane_r};
     launch_lp_convert(D->kind, st, ca);
     // W is stored times 2^s with 2^s max(nu) in [1, 2) so that fp16 keeps it normal
     double* dmax = nullptr;

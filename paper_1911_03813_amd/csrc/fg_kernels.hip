@@ -306,30 +306,22 @@ __global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
             Quad<T> q4;
 #pragma unroll
             for (int v = 0; v < 4; ++v) q4.e[v] = acc[m][t][v];
-            vstore4(pp + ((m * NT + t) * 64 + lane) * 4, q4);
+            xput4(pp + ((m * NT + t) * 64 + lane) * 4, q4);
           }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // each wave's stores are visible device-wide
-        __syncthreads();                                      // ... before the flag is raised
-        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        xput_complete();   // each wave's stores are done (visible device-wide)
+        __syncthreads();   // ... before the flag is raised
+        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         if (ke < KC) {
           // the next block holds chunks [ke, KC) of this slab
-          int spins = 0;
-          while (__builtin_amdgcn_readfirstlane(
-                     __hip_atomic_load(a.flag + blk + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > (1 << 24)) {
-              __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-          }
+          xwait_flag(a.flag + blk + 1, a.err);
           const T* pp = a.part + (blk + 1) * PART + (int64_t)wave * (MT * NT * 4 * 64);
 #pragma unroll
           for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
               Quad<T> q4;
-              vload4(q4, pp + ((m * NT + t) * 64 + lane) * 4);
+              xget4(q4, pp + ((m * NT + t) * 64 + lane) * 4);
 #pragma unroll
               for (int v = 0; v < 4; ++v) acc[m][t][v] += q4.e[v];
             }
@@ -340,11 +332,12 @@ __global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           const int64_t b = (int64_t)NW * MT * sl + MT * wave + m;   // 16-observation block
-          double nl[4];
+          double nl[4];   // clamped loads without branches: issued together
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int64_t l = 16 * b + Mfma<T>::row(g, v);
-            nl[v] = (l < a.p) ? a.nu[l] : 0.0;
+            const double x = a.nu[l < a.p ? l : (int64_t)a.p - 1];
+            nl[v] = (l < a.p) ? x : 0.0;
           }
 #pragma unroll
           for (int t = 0; t < NT; ++t) {

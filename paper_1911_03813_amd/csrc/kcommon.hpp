@@ -101,6 +101,76 @@ __device__ __forceinline__ void load_tail(Quad<T>& q, const T* col, int64_t i, i
   }
 }
 
+// Hand-off of a stream-K partial result between blocks, which may run on
+// different XCDs: each XCD has its own L2, and plain accesses are not
+// coherent between them.  The partial moves through relaxed device-scope
+// atomic accesses, which the hardware keeps coherent across the XCDs by
+// themselves.  The writer stores it with xput4, waits with xput_complete
+// until those stores are done, and only then (after a block barrier) raises
+// the flag; the reader reads it with xget4 after it has seen the flag.  This
+// avoids the L2-wide write-back and invalidation that device-scope release
+// and acquire fences perform, which cost far more than the partial itself.
+__device__ __forceinline__ void xput64(void* p, uint64_t v) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t xget64(const void* p) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t pack2(float x, float y) {
+  return (uint64_t)__builtin_bit_cast(uint32_t, x) | ((uint64_t)__builtin_bit_cast(uint32_t, y) << 32);
+}
+__device__ __forceinline__ void unpack2(uint64_t b, float& x, float& y) {
+  x = __builtin_bit_cast(float, (uint32_t)b);
+  y = __builtin_bit_cast(float, (uint32_t)(b >> 32));
+}
+__device__ __forceinline__ void xput4(float* p, const Quad<float>& q) {
+  xput64(p, pack2(q.e[0], q.e[1]));
+  xput64(p + 2, pack2(q.e[2], q.e[3]));
+}
+__device__ __forceinline__ void xput4(double* p, const Quad<double>& q) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) xput64(p + e, __builtin_bit_cast(uint64_t, q.e[e]));
+}
+__device__ __forceinline__ void xget4(Quad<float>& q, const float* p) {
+  unpack2(xget64(p), q.e[0], q.e[1]);
+  unpack2(xget64(p + 2), q.e[2], q.e[3]);
+}
+__device__ __forceinline__ void xget4(Quad<double>& q, const double* p) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) q.e[e] = __builtin_bit_cast(double, xget64(p + e));
+}
+__device__ __forceinline__ void xput4(float* p, v4f v) {
+  xput64(p, pack2(v[0], v[1]));
+  xput64(p + 2, pack2(v[2], v[3]));
+}
+__device__ __forceinline__ v4f xget4v(const float* p) {
+  v4f v;
+  float x, y;
+  unpack2(xget64(p), x, y);
+  v[0] = x; v[1] = y;
+  unpack2(xget64(p + 2), x, y);
+  v[2] = x; v[3] = y;
+  return v;
+}
+// every store this thread issued is complete (s_waitcnt with all counts 0)
+__device__ __forceinline__ void xput_complete() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Spin until a hand-off flag is raised (relaxed device-scope loads), giving
+// up after a bounded number of polls: then *err is set and the caller goes
+// on with whatever the partial holds, so that every wave still exits.
+__device__ __forceinline__ void xwait_flag(const int* flag, int* err) {
+  int spins = 0;
+  while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > (1 << 24)) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  // keeps the compiler from moving the partial's reads above the wait
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // x^k for a small non-negative integer k (k is uniform across the wave).
 __device__ __forceinline__ double ipow(double x, int k) {
   double r = 1.0;

@@ -9,13 +9,18 @@
 // 2^s in fp64.
 //
 // Layout (prepared once per data set, see symtd_data_create):
-//   Vc  column-major n x p, leading dimension ldc = n rounded up to the chunk
-//       (rows past n zero): the first product's operand (covariates contiguous)
-//   Vr  row-major n x p, leading dimension ldr = p rounded up to 128 (columns
-//       past p zero): the second product's operand (observations contiguous)
+//   Vc  column-major n x p: kc_len = n rounded up to LP_PAD covariates per
+//       column (rows past n zero), column stride ldc = kc_len + LP_SKEW: the
+//       first product's operand (covariates contiguous)
+//   Vr  row-major n x p: kr_len = p rounded up to LP_PAD observations per row
+//       (columns past p zero), row stride ldr = kr_len + LP_SKEW: the second
+//       product's operand (observations contiguous)
 // per evaluation:
-//   Ac  A in ldc rows x rp columns (zero padded), like Vc
-//   W   column-major ldr x rp (observations contiguous), written by gemm1
+//   Ac  A as kc_len rows x rp columns (zero padded), stride ldc, like Vc
+//   W   unit-major kr_len x rp: observation l of column j at
+//       ((l / 8) rp + j) 8 + l % 8, so that a unit (8 observations) of
+//       consecutive columns is contiguous for both gemm1's stores and
+//       gemm2's loads
 // bf16x3 keeps a hi and a lo plane of each, `plane` elements apart.
 #pragma once
 
@@ -26,27 +31,49 @@ namespace symtd {
 
 enum LpKind { LP_F16 = 0, LP_BF16X3 = 1 };
 
+// Shape of both products: waves per block, 16-row subtiles per wave, bytes of
+// one column run per chunk and plane, and LDS stages.
+#ifndef SYMTD_LP_MT
+#define SYMTD_LP_MT 2
+#endif
+#ifndef SYMTD_LP_RUN
+#define SYMTD_LP_RUN 256
+#endif
+#ifndef SYMTD_LP_RUN_BF
+#define SYMTD_LP_RUN_BF 128
+#endif
+#ifndef SYMTD_LP_STAGES
+#define SYMTD_LP_STAGES 2
+#endif
 constexpr int LP_WAVES = 4;
-constexpr int LP_MT = 2;                 // 16-row subtiles per wave
-constexpr int LP_SLAB = 16 * LP_MT * LP_WAVES;   // 128 rows (gemm1: observations, gemm2: covariates)
+constexpr int LP_MT = SYMTD_LP_MT;
+constexpr int LP_SLAB = 16 * LP_MT * LP_WAVES;   // rows of a block (gemm1: observations, gemm2: covariates)
 constexpr int LP_NT_MAX = 7;             // 16-column subtiles per launch
-// k values per chunk: one 256-byte run per column (fp16), 128 bytes per plane (bf16x3)
-constexpr int lp_chunk(int kind) { return kind == LP_F16 ? 128 : 64; }
-constexpr int LP_PAD = 128;              // ldr / ldc multiple (covers both chunks)
+constexpr int LP_STAGES = SYMTD_LP_STAGES;
+// k values per chunk: a run of SYMTD_LP_RUN (fp16) or SYMTD_LP_RUN_BF (bf16x3,
+// per plane) bytes per column
+constexpr int lp_chunk(int kind) { return (kind == LP_F16 ? SYMTD_LP_RUN : SYMTD_LP_RUN_BF) / 2; }
+constexpr int LP_PAD = 256;              // ldr / ldc multiple (whole chunks, whole slabs)
+
+// ldc / ldr are column / row strides; kc_len / kr_len (multiples of LP_PAD)
+// are the extents the products run over (zero beyond the data).  The strides
+// exceed the extents by LP_SKEW elements so that a chunk's column reads do not
+// fall on a power-of-two stride.
+constexpr int LP_SKEW = 64;
 
 struct LpG1Args {
-  const void* Vc; int64_t ldc; int64_t vplane;   // elements between the hi and lo planes
+  const void* Vc; int64_t ldc; int64_t kc_len; int64_t vplane;   // vplane: elements between the hi and lo planes
   const double* nu; int n; int p;
   const void* Ac; int64_t aplane;
   int col0, rp, nslab, nblocks, d;
   double wscale;                                 // 2^s (fp16) or 1
-  void* W; int64_t ldr; int64_t wplane;
+  void* W; int64_t kr_len; int64_t wplane;       // W rows: kr_len observations
   double* wpart;                                 // [4 nblocks][rp]
   float* part; int* flag; int* err;              // stream-K hand-off
 };
 
 struct LpG2Args {
-  const void* Vr; int64_t ldr; int64_t vplane;
+  const void* Vr; int64_t ldr; int64_t kr_len; int64_t vplane;
   const void* W; int64_t wplane;
   int n; int col0; int rp;
   int nslab;                                     // ceil(n / LP_SLAB)
@@ -56,12 +83,12 @@ struct LpG2Args {
 
 struct LpPackArgs {
   const float* A; int64_t lda; int n; int r;
-  void* Ac; int64_t ldc; int rp; int64_t aplane;
+  void* Ac; int64_t ldc; int64_t kc_len; int rp; int64_t aplane;
 };
 
 struct LpConvArgs {
   const float* V; int64_t ldv; int n; int p;
-  void* Vc; int64_t ldc; void* Vr; int64_t ldr; int64_t plane_c, plane_r;
+  void* Vc; int64_t ldc; int64_t kc_len; void* Vr; int64_t ldr; int64_t kr_len; int64_t plane_c, plane_r;
 };
 
 void launch_lp_gemm1(int kind, int nt, dim3 grid, hipStream_t st, const LpG1Args& a);

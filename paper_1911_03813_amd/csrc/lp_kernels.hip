@@ -33,6 +33,7 @@ template <> struct LpT<LP_F16> {
                                                   0, 0, 0);
   }
   static __device__ __forceinline__ void split(double x, E* out) { out[0] = (E)(float)x; }
+  static __device__ __forceinline__ void split(float x, E* out) { out[0] = (E)x; }
 };
 template <> struct LpT<LP_BF16X3> {
   using E = __bf16;
@@ -48,6 +49,12 @@ template <> struct LpT<LP_BF16X3> {
     const __bf16 hi = (__bf16)xf;
     out[0] = hi;
     out[1] = (__bf16)(float)(x - (double)(float)hi);
+  }
+  // from fp32 the difference x - hi is exact
+  static __device__ __forceinline__ void split(float x, E* out) {
+    const __bf16 hi = (__bf16)x;
+    out[0] = hi;
+    out[1] = (__bf16)(x - (float)hi);
   }
 };
 
@@ -138,6 +145,52 @@ __device__ __forceinline__ void lp_compute(const u4* lx, const u4* ly, int wave,
 
 }  // namespace
 
+// The chunk loop of a block over nk chunks, with LP_STAGES LDS stages: chunk
+// q lives in stage q mod LP_STAGES; `issue(stage, q)` starts its DMA and
+// `use(stage)` multiplies it.  A wave waits (vmcnt) until its pieces of the
+// chunk it needs have landed, counting the later chunks still in flight, and
+// the barrier then guarantees every wave's pieces are in and that the stage
+// about to be refilled has been read by all.
+#define LP_CHUNK_LOOP                                                                                     \
+  auto chunk_loop = [&](int64_t nk, auto issue, auto use) {                                               \
+    constexpr int DPC = S::DPC;                                                                           \
+    auto arrive = [&](int64_t later) {                                                                    \
+      if (LP_STAGES > 2 && later >= 1) wait_vm<DPC>(); else wait_vm<0>();                                  \
+      __syncthreads();                                                                                    \
+    };                                                                                                    \
+    if constexpr (LP_STAGES == 3) {                                                                       \
+      if (nk <= 0) return;                                                                                \
+      issue(lx0, ly0, 0);                                                                                 \
+      if (nk > 1) issue(lx1, ly1, 1);                                                                     \
+      int64_t q = 0;                                                                                      \
+      for (; q + 3 <= nk; q += 3) {                                                                       \
+        arrive(min((int64_t)1, nk - 1 - q));                                                              \
+        if (q + 2 < nk) issue(lx2, ly2, q + 2);                                                           \
+        use(lx0, ly0);                                                                                    \
+        arrive(min((int64_t)1, nk - 2 - q));                                                              \
+        if (q + 3 < nk) issue(lx0, ly0, q + 3);                                                           \
+        use(lx1, ly1);                                                                                    \
+        arrive(min((int64_t)1, nk - 3 - q));                                                              \
+        if (q + 4 < nk) issue(lx1, ly1, q + 4);                                                           \
+        use(lx2, ly2);                                                                                    \
+      }                                                                                                   \
+      if (q < nk) { arrive(min((int64_t)1, nk - 1 - q)); use(lx0, ly0); }                                  \
+      if (q + 1 < nk) { arrive(0); use(lx1, ly1); }                                                       \
+    } else {                                                                                              \
+      if (nk > 0) issue(lx0, ly0, 0);                                                                     \
+      int64_t q = 0;                                                                                      \
+      for (; q + 2 <= nk; q += 2) {                                                                       \
+        arrive(0);                                                                                        \
+        issue(lx1, ly1, q + 1);                                                                           \
+        use(lx0, ly0);                                                                                    \
+        arrive(0);                                                                                        \
+        if (q + 2 < nk) issue(lx0, ly0, q + 2);                                                           \
+        use(lx1, ly1);                                                                                    \
+      }                                                                                                   \
+      if (q < nk) { arrive(0); use(lx0, ly0); }                                                           \
+    }                                                                                                     \
+  };
+
 // ---------------------------------------------------------------------------
 // gemm1: Z = Vc' Ac for one column group, stream-K over (slab, chunk) as in
 // the fp32 kernel; epilogue W = 2^s nu z^{d-1} (column-major, ld ldr) and
@@ -150,13 +203,14 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
   constexpr int PL = S::PL;
   constexpr int KCH = lp_chunk(KIND);
   constexpr int PART = LP_WAVES * LP_MT * NT * 256;
-  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256];
-  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256];
+  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256], lx2[LP_STAGES > 2 ? S::XP * 256 : 1];
+  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256], ly2[LP_STAGES > 2 ? S::YP * 256 : 1];
+  LP_CHUNK_LOOP
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, c = lane & 15;
   const int64_t B = a.nblocks, blk = blockIdx.x;
-  const int64_t KC = a.ldc / KCH;
+  const int64_t KC = a.kc_len / KCH;
   const int64_t U = (int64_t)a.nslab * KC;
   const int64_t u0 = blk * U / B, u1 = (blk + 1) * U / B;
   const E* V = (const E*)a.Vc;
@@ -184,87 +238,84 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
     };
     lp_dma<KIND, NT>(lx, ly, tid, wave, xs, ys);
   };
-  auto arrive = [&]() {
-    wait_vm<0>();
-    __syncthreads();
+
+  // weights of the slab being multiplied, for its owner's epilogue: loaded
+  // (clamped, without branches) when the slab begins, so that the loads are
+  // long complete when the epilogue needs them
+  // (kept as loaded: converting at once would wait for them there)
+  double nl[LP_MT][4];
+  auto load_nu = [&](int64_t sl) {
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t l = (int64_t)LP_SLAB * sl + 16 * (LP_MT * wave + m) + 4 * g + v;
+        nl[m][v] = a.nu[l < a.p ? l : (int64_t)a.p - 1];
+      }
   };
 
-  if (u0 < u1) {
-    int64_t sl = u0 / KC, kb = u0 - sl * KC;
-    const int64_t sl_last = (u1 - 1) / KC;
-    while (true) {
-      const int64_t ke = (sl == sl_last) ? u1 - sl * KC : KC;
-      const int64_t nk = ke - kb;
-      dma(lx0, ly0, sl, kb);
-      int64_t q = 0;
-      for (; q + 2 <= nk; q += 2) {
-        arrive();
-        dma(lx1, ly1, sl, kb + q + 1);
-        lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
-        arrive();
-        if (q + 2 < nk) dma(lx0, ly0, sl, kb + q + 2);
-        lp_compute<KIND, NT>(lx1, ly1, wave, g, c, acc);
-      }
-      if (q < nk) {
-        arrive();
-        lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
-      }
-      __syncthreads();   // every stage is read before the next slab overwrites it
-
+  // end of this block's part of slab sl (chunks kb .. ke-1): publish the
+  // partial (not the owner) or merge and run the epilogue (owner)
+  auto finish_slab = [&](int64_t sl, int64_t kb, int64_t ke) {
       if (kb > 0) {
         // not the owner: publish this block's partial for the previous block
         float* pp = a.part + blk * PART + (int64_t)wave * (LP_MT * NT * 256);
-#pragma unroll
+  #pragma unroll
         for (int m = 0; m < LP_MT; ++m)
-#pragma unroll
+  #pragma unroll
           for (int t = 0; t < NT; ++t)
-            *reinterpret_cast<f4*>(pp + ((m * NT + t) * 64 + lane) * 4) = acc[m][t];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            xput4(pp + ((m * NT + t) * 64 + lane) * 4, acc[m][t]);
+        xput_complete();   // each wave's stores are done (visible device-wide)
+        __syncthreads();   // ... before the flag is raised
+        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
+        // owner (nl holds the slab's weights, loaded when the slab began)
         if (ke < KC) {
-          int spins = 0;
-          while (__builtin_amdgcn_readfirstlane(
-                     __hip_atomic_load(a.flag + blk + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > (1 << 24)) {
-              __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-          }
+          xwait_flag(a.flag + blk + 1, a.err);
           const float* pp = a.part + (blk + 1) * PART + (int64_t)wave * (LP_MT * NT * 256);
-#pragma unroll
+  #pragma unroll
           for (int m = 0; m < LP_MT; ++m)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[m][t] += *reinterpret_cast<const f4*>(pp + ((m * NT + t) * 64 + lane) * 4);
+  #pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] += xget4v(pp + ((m * NT + t) * 64 + lane) * 4);
           __syncthreads();
           if (tid == 0) __hip_atomic_store(a.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // epilogue: acc[m][t][v] = z at l = 16 b + 4 g + v, column col0 + 16 t + c
+        // epilogue: acc[m][t][v] = z at l = lb + v, column col0 + 16 t + c.
+        // w = nu z^(d-1) in fp32 (its 16-bit storage rounds far more); the
+        // power runs over all of the lane's values at once, and the sum of
+        // w z is kept in fp64.
+        f4 zp[LP_MT][NT];
+#pragma unroll
+        for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) zp[m][t] = f4{1.0f, 1.0f, 1.0f, 1.0f};
+        for (int e = 0; e < dm1; ++e)
+#pragma unroll
+          for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) zp[m][t] *= acc[m][t];
+        const float ws = (float)a.wscale;
 #pragma unroll
         for (int m = 0; m < LP_MT; ++m) {
           const int64_t lb = (int64_t)LP_SLAB * sl + 16 * (LP_MT * wave + m) + 4 * g;
-          double nl[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) nl[v] = (lb + v < a.p) ? a.nu[lb + v] : 0.0;
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             E out[PL][4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const double z = (double)acc[m][t][v];
-              const double wv = nl[v] * ipow(z, dm1);
-              wsum[t] += wv * z;
+              const float wv = (lb + v < a.p ? (float)nl[m][v] : 0.0f) * zp[m][t][v];
+              wsum[t] += (double)wv * (double)acc[m][t][v];
               E parts[PL];
-              LpT<KIND>::split(a.wscale * wv, parts);
+              LpT<KIND>::split(ws * wv, parts);
 #pragma unroll
               for (int pl = 0; pl < PL; ++pl) out[pl][v] = parts[pl];
             }
+            // W is unit-major: the 8 observations of unit u of column j at
+            // (u rp + j) 8; this lane's 4 observations are half of unit lb / 8
             const int64_t col = a.col0 + 16 * t + c;
 #pragma unroll
             for (int pl = 0; pl < PL; ++pl) {
-              E* dst = (E*)a.W + pl * a.wplane + col * a.ldr + lb;
+              E* dst = (E*)a.W + pl * a.wplane + ((lb >> 3) * a.rp + col) * 8 + (lb & 7);
               uint2 packed;
               __builtin_memcpy(&packed, out[pl], sizeof(packed));
               *reinterpret_cast<uint2*>(dst) = packed;
@@ -273,12 +324,37 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
         }
       }
 #pragma unroll
-      for (int m = 0; m < LP_MT; ++m)
+    for (int m = 0; m < LP_MT; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
-      if (sl == sl_last) break;
-      ++sl;
-      kb = 0;
+      for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
+  };
+
+  if (u0 < u1) {
+    // the block's (slab, chunk) units in order through one continuous
+    // two-stage pipeline: a slab's epilogue runs while the next chunk (the
+    // next slab's first) is already in flight
+    static_assert(LP_STAGES == 2, "the first product's unit loop is written for two stages");
+    // (slab, chunk) of the unit being multiplied and of the next one issued
+    int64_t sl = u0 / KC, kc = u0 - sl * KC;
+    int64_t isl = sl, ikc = kc;
+    auto issue_next = [&](int stage) {
+      dma(stage ? lx1 : lx0, stage ? ly1 : ly0, isl, ikc);
+      if (++ikc == KC) { ikc = 0; ++isl; }
+    };
+    issue_next(0);
+    int64_t kb = kc;           // first chunk of the current slab segment
+    for (int64_t u = u0; u < u1; ++u) {
+      const int st = (int)((u - u0) & 1);
+      wait_vm<0>();
+      __syncthreads();         // chunk u has landed everywhere; the other stage is free
+      if (kc == 0) load_nu(sl);
+      if (u + 1 < u1) issue_next(st ^ 1);
+      lp_compute<KIND, NT>(st ? lx1 : lx0, st ? ly1 : ly0, wave, g, c, acc);
+      if (kc == KC - 1 || u + 1 == u1) {
+        finish_slab(sl, kb, kc + 1);
+        kb = 0;
+      }
+      if (++kc == KC) { kc = 0; ++sl; }
     }
   }
 #pragma unroll
@@ -299,13 +375,19 @@ __global__ __launch_bounds__(256) void k_lp_gemm2(LpG2Args a) {
   using S = LpStage<KIND, NT>;
   using E = typename LpT<KIND>::E;
   constexpr int KCH = lp_chunk(KIND);
-  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256];
-  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256];
+  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256], lx2[LP_STAGES > 2 ? S::XP * 256 : 1];
+  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256], ly2[LP_STAGES > 2 ? S::YP * 256 : 1];
+  LP_CHUNK_LOOP
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, c = lane & 15;
-  const int slab = blockIdx.x % a.nslab, split = blockIdx.x / a.nslab;
-  const int64_t KC = a.ldr / KCH;
+  // block -> (slab, split): the slabs of one split get ids with the same
+  // residue mod 8, so they run on one XCD and share its L2 for W
+  const int64_t bid = blockIdx.x;
+  const int split = (int)(bid % 8 + 8 * (bid / (8 * (int64_t)a.nslab)));
+  const int slab = (int)((bid / 8) % a.nslab);
+  if (split >= a.nsplit) return;
+  const int64_t KC = a.kr_len / KCH;
   const int64_t kb = (int64_t)split * a.chunks_per_split;
   const int64_t ke = min(KC, kb + a.chunks_per_split);
   const E* Vr = (const E*)a.Vr;
@@ -323,31 +405,13 @@ __global__ __launch_bounds__(256) void k_lp_gemm2(LpG2Args a) {
       return Vr + pl * a.vplane + i * a.ldr + k0 + 8 * q;
     };
     auto ys = [&](int pl, int col, int q) -> const void* {
-      return W + pl * a.wplane + (int64_t)(a.col0 + col) * a.ldr + k0 + 8 * q;
+      return W + pl * a.wplane + ((k0 >> 3) + q) * (int64_t)a.rp * 8 + (int64_t)(a.col0 + col) * 8;
     };
     lp_dma<KIND, NT>(lx, ly, tid, wave, xs, ys);
   };
-  auto arrive = [&]() {
-    wait_vm<0>();
-    __syncthreads();
-  };
   const int64_t nk = ke - kb;
-  if (nk > 0) {
-    dma(lx0, ly0, kb);
-    int64_t q = 0;
-    for (; q + 2 <= nk; q += 2) {
-      arrive();
-      dma(lx1, ly1, kb + q + 1);
-      lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
-      arrive();
-      if (q + 2 < nk) dma(lx0, ly0, kb + q + 2);
-      lp_compute<KIND, NT>(lx1, ly1, wave, g, c, acc);
-    }
-    if (q < nk) {
-      arrive();
-      lp_compute<KIND, NT>(lx0, ly0, wave, g, c, acc);
-    }
-  }
+  chunk_loop(nk, [&](u4* lx, u4* ly, int64_t q) { dma(lx, ly, kb + q); },
+             [&](const u4* lx, const u4* ly) { lp_compute<KIND, NT>(lx, ly, wave, g, c, acc); });
   // acc[m][t][v] = Y[slab rows + 16 (MT wave + m) + 4 g + v][col0 + 16 t + c]
 #pragma unroll
   for (int m = 0; m < LP_MT; ++m) {
@@ -367,14 +431,14 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_lp_pack_a(LpPackArgs a) {
   using E = typename LpT<KIND>::E;
   constexpr int PL = LpT<KIND>::PLANES;
-  const int64_t total = (int64_t)a.rp * a.ldc;
+  const int64_t total = (int64_t)a.rp * a.kc_len;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t j = e / a.ldc, k = e - j * a.ldc;
+    const int64_t j = e / a.kc_len, k = e - j * a.kc_len;
     const double x = (k < a.n && j < a.r) ? (double)a.A[j * a.lda + k] : 0.0;
     E parts[PL];
     LpT<KIND>::split(x, parts);
 #pragma unroll
-    for (int pl = 0; pl < PL; ++pl) ((E*)a.Ac)[pl * a.aplane + e] = parts[pl];
+    for (int pl = 0; pl < PL; ++pl) ((E*)a.Ac)[pl * a.aplane + j * a.ldc + k] = parts[pl];
   }
 }
 
@@ -384,14 +448,14 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_lp_conv_c(LpConvArgs a) {
   using E = typename LpT<KIND>::E;
   constexpr int PL = LpT<KIND>::PLANES;
-  const int64_t total = (int64_t)a.p * a.ldc;
+  const int64_t total = (int64_t)a.p * a.kc_len;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t l = e / a.ldc, k = e - l * a.ldc;
+    const int64_t l = e / a.kc_len, k = e - l * a.kc_len;
     const double x = k < a.n ? (double)a.V[l * a.ldv + k] : 0.0;
     E parts[PL];
     LpT<KIND>::split(x, parts);
 #pragma unroll
-    for (int pl = 0; pl < PL; ++pl) ((E*)a.Vc)[pl * a.plane_c + e] = parts[pl];
+    for (int pl = 0; pl < PL; ++pl) ((E*)a.Vc)[pl * a.plane_c + l * a.ldc + k] = parts[pl];
   }
 }
 
@@ -409,7 +473,7 @@ __global__ __launch_bounds__(256) void k_lp_conv_r(LpConvArgs a) {
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
     const int64_t i = i0 + yy, l = l0 + tx;
-    if (i < a.n && l < a.ldr) {
+    if (i < a.n && l < a.kr_len) {
       E parts[PL];
       LpT<KIND>::split((double)tile[tx][yy], parts);
 #pragma unroll
@@ -472,15 +536,15 @@ void launch_lp_gemm2(int kind, int nt, dim3 grid, hipStream_t st, const LpG2Args
   else g2<LP_BF16X3>(nt, grid, st, a);
 }
 void launch_lp_pack_a(int kind, hipStream_t st, const LpPackArgs& a) {
-  const int64_t total = (int64_t)a.rp * a.ldc;
+  const int64_t total = (int64_t)a.rp * a.kc_len;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
   if (kind == LP_F16) hipLaunchKernelGGL(k_lp_pack_a<LP_F16>, dim3(blocks), dim3(256), 0, st, a);
   else hipLaunchKernelGGL(k_lp_pack_a<LP_BF16X3>, dim3(blocks), dim3(256), 0, st, a);
 }
 void launch_lp_convert(int kind, hipStream_t st, const LpConvArgs& a) {
-  const int64_t total = (int64_t)a.p * a.ldc;
+  const int64_t total = (int64_t)a.p * a.kc_len;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-  const dim3 tgrid((unsigned)((a.ldr + 31) / 32), (unsigned)((a.n + 31) / 32));
+  const dim3 tgrid((unsigned)((a.kr_len + 31) / 32), (unsigned)((a.n + 31) / 32));
   if (kind == LP_F16) {
     hipLaunchKernelGGL(k_lp_conv_c<LP_F16>, dim3(blocks), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_lp_conv_r<LP_F16>, tgrid, dim3(256), 0, st, a);

@@ -131,7 +131,13 @@ symtd_status symtd_fg_data(symtd_ctx* ctx, void* stream, const symtd_data* data,
  * lambda[m*r .. m*r + r - 1]; its f is f[m] and its gradients occupy the same
  * columns of g_lambda and G_A.  The two products read V once for all models
  * (their columns side by side); the model terms B, C, u are formed per model.
- * symtd_fg is this call with models = 1.  Other arguments as in symtd_fg.
+ * 1 <= models <= 1024.  symtd_fg is this call with models = 1.  Other
+ * arguments as in symtd_fg.
+ *
+ * An evaluation is four kernels in order on `stream` (no other stream is
+ * used): the factor copy with the Gram matrices A'A, the two products, and a
+ * closing kernel for G_A, g_lambda and f.  Calls that overlap on one context
+ * race (they share its workspace and counters).
  */
 symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt,
                             const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
@@ -360,27 +366,28 @@ void symtd_server_destroy(symtd_server* srv);
  *                         observation slabs; larger requests are clamped)
  *   SYMTD_TUNE_G2_SPLITS  splits of the observations in the second product V W
  *                         (0 = automatic: about one block per compute unit)
- *   SYMTD_TUNE_SERIAL     1 = run the small model-term kernels (A'A, A D C) on
- *                         the caller's stream before the products; 0 (default)
- *                         = on the context's side stream, overlapped with them
  *   SYMTD_TUNE_GRAPH      grouped engine (batched solve, server): 1 (default)
  *                         = capture one evaluation step as a hipGraph and
  *                         replay it; 0 = launch the step's kernels eagerly
  * Values must be >= 0; results do not depend on them beyond rounding order.
  */
 typedef enum symtd_tune_key {
-  SYMTD_TUNE_G1_BLOCKS = 0, SYMTD_TUNE_G2_SPLITS = 1, SYMTD_TUNE_SERIAL = 2, SYMTD_TUNE_GRAPH = 3
+  SYMTD_TUNE_G1_BLOCKS = 0, SYMTD_TUNE_G2_SPLITS = 1, SYMTD_TUNE_GRAPH = 3   /* 2: unused */
 } symtd_tune_key;
 symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value);
 
 /*
- * Per-kernel timing. While enabled, every kernel the context launches is
- * bracketed by HIP events on the launch stream; symtd_profile_read
- * synchronises those events and returns, for kernel `which`, the summed
- * duration in milliseconds and the number of launches since the last
- * reset. Kernel ids are listed by symtd_profile_name (NULL past the end).
+ * Per-kernel timing. Every launch of a kernel id whose bit is set in `mask`
+ * (bit k = id k; 0 = off, 0xffffffff = all) is bracketed by HIP events on
+ * its launch stream; symtd_profile_read synchronises those events and
+ * returns, for kernel `which`, the summed duration in milliseconds and the
+ * number of launches since the last reset. symtd_profile_reset returns the
+ * events to a pool that later launches reuse, so that timing a warmed-up
+ * loop creates no events. Kernel ids are listed by symtd_profile_name (NULL
+ * past the end): gemm1, gemm2, prep (factor copy and A'A), final (G_A and the
+ * scalars), normx, reduce.
  */
-symtd_status symtd_profile_enable(symtd_ctx* ctx, int enable);
+symtd_status symtd_profile_enable(symtd_ctx* ctx, uint32_t mask);
 symtd_status symtd_profile_reset(symtd_ctx* ctx);
 symtd_status symtd_profile_read(symtd_ctx* ctx, int which, double* total_ms, int64_t* launches);
 const char* symtd_profile_name(int which);

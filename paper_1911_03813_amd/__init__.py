@@ -133,7 +133,7 @@ SIGNATURES = {
     "symtd_server_destroy": (None, [_vp]),
     "symtd_solve_batched": (_int, [_vp, _vp, _i64, _c.POINTER(Problem), _c.POINTER(SolveOpts),
                                    _c.POINTER(SolveResult)]),
-    "symtd_profile_enable": (_int, [_vp, _int]),
+    "symtd_profile_enable": (_int, [_vp, ctypes.c_uint32]),
     "symtd_profile_reset": (_int, [_vp]),
     "symtd_profile_read": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
     "symtd_profile_name": (_c.c_char_p, [_int]),
@@ -559,7 +559,7 @@ def symtd_normX(ctx: Context, V, nu, d: int, out=None, stream=None):
     return a
 
 
-TUNE_G1_BLOCKS, TUNE_G2_SPLITS, TUNE_SERIAL, TUNE_GRAPH = 0, 1, 2, 3
+TUNE_G1_BLOCKS, TUNE_G2_SPLITS, TUNE_GRAPH = 0, 1, 3
 
 
 def symtd_set_tuning(ctx: Context, key: int, value: int):
@@ -567,8 +567,19 @@ def symtd_set_tuning(ctx: Context, key: int, value: int):
     _check(ctx, lib().symtd_set_tuning(ctx.handle, int(key), int(value)))
 
 
-def symtd_profile_enable(ctx: Context, enable: bool = True):
-    _check(ctx, lib().symtd_profile_enable(ctx.handle, int(bool(enable))))
+def symtd_profile_enable(ctx: Context, enable: bool = True, kernels=None):
+    """Time every launch of the named kernels (profile_names(); all when
+    kernels is None) while enabled; off when enable is false."""
+    if not enable:
+        mask = 0
+    elif kernels is None:
+        mask = 0xFFFFFFFF
+    else:
+        names = profile_names()
+        mask = 0
+        for k in kernels:
+            mask |= 1 << names.index(k)
+    _check(ctx, lib().symtd_profile_enable(ctx.handle, mask))
 
 
 def symtd_profile_reset(ctx: Context):

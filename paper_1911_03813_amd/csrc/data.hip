@@ -46,51 +46,39 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
   int nsplit = std::max(1, (ctx->cu_count + nslab2 - 1) / nslab2);
   const int cps = (int)((KC2 + nsplit - 1) / nsplit);
   nsplit = (int)((KC2 + cps - 1) / cps);
-  const int gsplit = (int)((n + 127) / 128);
   if (nblocks1 > ctx->nflags) return ctx->fail(SYMTD_EINVAL, "internal: %d blocks exceed the flag array", nblocks1);
 
-  auto plan = [&](Carver& c, void** Ac, void** W, double** wpart, float** part, float** Ypart, double** Bpart,
-                  double** B, double** C, double** YM, double** fpart) {
+  auto plan = [&](Carver& c, void** Ac, void** W, double** wpart, float** part, float** Ypart, double** B,
+                  double** C, double** fpart) {
     *Ac = c.take<uint16_t>((size_t)PL * D->ldc * rp);
     *W = c.take<uint16_t>((size_t)PL * D->kr_len * rp);
     *wpart = c.take<double>((size_t)LP_WAVES * nblocks1 * rp);
     *part = c.take<float>((size_t)nblocks1 * LP_WAVES * LP_MT * LP_NT_MAX * 256);
     *Ypart = c.take<float>((size_t)nsplit * rp * npad);
-    *Bpart = c.take<double>((size_t)gsplit * r * r);
     *B = c.take<double>((size_t)r * r);
     *C = c.take<double>((size_t)r * r);
-    *YM = c.take<double>((size_t)n * r);
     *fpart = c.take<double>((size_t)r);
   };
   void *Ac, *W;
-  double *wpart, *Bpart, *B, *C, *YM, *fpart;
+  double *wpart, *B, *C, *fpart;
   float *part, *Ypart;
   Carver sz(nullptr);
-  plan(sz, &Ac, &W, &wpart, &part, &Ypart, &Bpart, &B, &C, &YM, &fpart);
+  plan(sz, &Ac, &W, &wpart, &part, &Ypart, &B, &C, &fpart);
   symtd_status s = ctx->reserve(sz.off + 256);
   if (s != SYMTD_OK) return s;
   Carver cv(ctx->ws);
-  plan(cv, &Ac, &W, &wpart, &part, &Ypart, &Bpart, &B, &C, &YM, &fpart);
+  plan(cv, &Ac, &W, &wpart, &part, &Ypart, &B, &C, &fpart);
   const int64_t aplane = D->ldc * rp, wplane = D->kr_len * rp;
-  hipStream_t side = ctx->tune_serial ? st : ctx->side;
+  const int rt = (int)((r + 15) / 16);
+  // four launches on the caller's stream: prep, gemm1, gemm2, final
 
-  (void)hipEventRecord(ctx->ev_fork, st);
-  (void)hipStreamWaitEvent(side, ctx->ev_fork, 0);
-  {
-    GramArgs<float> ga{A, lda, (int)n, (int)r, 1, Bpart};
-    const unsigned rt = (unsigned)((r + 15) / 16);
-    ctx->prof_begin(2, side);
-    launch_gram(dim3(rt, rt, (unsigned)gsplit), side, ga);
-    GramFinArgs gf{Bpart, gsplit, (int64_t)r * r, d, B, C};
-    launch_gram_fin(dim3((unsigned)((r * r + 255) / 256)), side, gf);
-    YModelArgs<float> ya{A, lda, (int)n, (int)r, 1, (int)rt, lambda, C, YM};
-    launch_ymodel(dim3((unsigned)((n + 63) / 64), rt), side, ya);
-    ctx->prof_end(side);
-    (void)hipEventRecord(ctx->ev_model, side);
-  }
+  // prep: the 16-bit copy of A, and B = A'A, C = B^{d-1} from the fp32 A
   {
     LpPackArgs pa{A, lda, (int)n, (int)r, Ac, D->ldc, D->kc_len, rp, aplane};
-    launch_lp_pack_a(kind, st, pa);
+    GramArgs<float> ga{A, lda, (int)n, (int)r, 1, rt, d, B, C};
+    ctx->prof_begin(2, st);
+    launch_lp_prep(kind, (int64_t)rt * rt, st, pa, ga);
+    ctx->prof_end(2, st);
   }
   for (int t0 = 0; t0 < nt_tot; t0 += LP_NT_MAX) {
     const int nt = std::min(LP_NT_MAX, nt_tot - t0);
@@ -98,33 +86,26 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
                 nblocks1, d, D->wscale, W, D->kr_len, wplane, wpart, part, ctx->flags, ctx->dev_err};
     ctx->prof_begin(0, st);
     launch_lp_gemm1(kind, nt, dim3(nblocks1), st, a1);
-    ctx->prof_end(st);
-  }
-  (void)hipEventRecord(ctx->ev_g1, st);
-  (void)hipStreamWaitEvent(side, ctx->ev_g1, 0);
-  {
-    FinalSArgs as{wpart, (int64_t)LP_WAVES * nblocks1, rp, B, C, lambda, (int)r, 1, alpha, fpart, f, g_lambda};
-    ctx->prof_begin(4, side);
-    launch_final_s(dim3((unsigned)r), side, as);
-    launch_final_f(dim3(1), side, as);
-    ctx->prof_end(side);
-    (void)hipEventRecord(ctx->ev_side, side);
+    ctx->prof_end(0, st);
   }
   for (int t0 = 0; t0 < nt_tot; t0 += LP_NT_MAX) {
     const int nt = std::min(LP_NT_MAX, nt_tot - t0);
     LpG2Args a2{D->Vr, D->ldr, D->kr_len, D->plane_r, W, wplane, (int)n, 16 * t0, rp, nslab2, nsplit, cps, Ypart, npad};
     ctx->prof_begin(1, st);
     launch_lp_gemm2(kind, nt, dim3((unsigned)(nslab2 * 8 * ((nsplit + 7) / 8))), st, a2);
-    ctx->prof_end(st);
+    ctx->prof_end(1, st);
   }
-  (void)hipStreamWaitEvent(st, ctx->ev_model, 0);
+  // G_A (Y unscaled by 1 / wscale), w, u, g_lambda, f
+  ctx->prof_begin(3, st);
   {
-    FinalGArgs<float> ag{Ypart, npad, rp, nsplit, YM, (int)n, (int)r, d, lambda, G, ldg, 1.0 / D->wscale};
-    ctx->prof_begin(3, st);
-    launch_final_G(dim3((unsigned)((n + 255) / 256), (unsigned)r), st, ag);
-    ctx->prof_end(st);
+    const int ct = (int)((r + FINAL_COLS - 1) / FINAL_COLS);
+    const int64_t ntile = ((n + 63) / 64) * ct;
+    FinalArgs<float> fa{Ypart, npad, rp, nsplit, 1.0 / D->wscale, A, lda, (int)n, (int)r, 1, ct, lambda, B, C, d,
+                        wpart, (int64_t)LP_WAVES * nblocks1, alpha, G, ldg, fpart, f, g_lambda, ctx->final_count,
+                        ntile};
+    launch_final(st, fa);
   }
-  (void)hipStreamWaitEvent(st, ctx->ev_side, 0);
+  ctx->prof_end(3, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ctx->hip_fail(e, "kernel launch (16-bit products)");
   return SYMTD_OK;

@@ -26,6 +26,7 @@
 
 #include "kcommon.hpp"
 #include "kernels.hpp"
+#include "model_dev.hpp"
 
 namespace symtd {
 
@@ -468,110 +469,52 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// pack_a: Apad[j][k] = A[k][j] for k < n, j < r, and 0 elsewhere (column-major,
-// leading dimension ldap = whole gemm1 chunks, rp columns)
+// prep: Apad[j][k] = A[k][j] for k < n, j < r, and 0 elsewhere (column-major,
+// leading dimension ldap = whole gemm1 chunks, rp columns), and the Gram
+// tiles of B = A'A, C = B^{d-1} (gram_tile, model_dev.hpp), in one launch of
+// 1024-thread blocks.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_pack_a(PackAArgs<T> a) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int j = blockIdx.y;
+__device__ __forceinline__ void pack_a_block(const PackAArgs<T>& a, int64_t bx, int j) {
+  const int64_t k = bx * GRAM_THREADS + threadIdx.x;
   if (k >= a.ldap) return;
   a.Apad[(int64_t)j * a.ldap + k] = (k < a.n && j < a.r) ? a.A[(int64_t)j * a.lda + k] : T(0);
 }
 
-// ---------------------------------------------------------------------------
-// gram: B = A'A in fp64.  gram_part: one 16 x 16 tile of B over 128 rows of
-// A per block; gram_fin: fixed-order sum over the row splits, C = B^{d-1}.
-// ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_part(GramArgs<T> a) {
-  __shared__ double sj[128][17];
-  __shared__ double sk[128][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int j0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
-  const int grp = blockIdx.z % a.ng, split = blockIdx.z / a.ng;
-  const T* Ag = a.A + (int64_t)grp * a.r * a.lda;
-  const int64_t i0 = (int64_t)split * 128;
-  for (int e = threadIdx.x; e < 128 * 16; e += 256) {
-    const int ii = e & 127, cc = e >> 7;
-    const int64_t i = i0 + ii;
-    const int j = j0 + cc, k = k0 + cc;
-    sj[ii][cc] = (i < a.n && j < a.r) ? (double)Ag[(int64_t)j * a.lda + i] : 0.0;
-    sk[ii][cc] = (i < a.n && k < a.r) ? (double)Ag[(int64_t)k * a.lda + i] : 0.0;
+__global__ __launch_bounds__(GRAM_THREADS) void k_prep(PrepArgs<T> a) {
+  __shared__ double lds[GRAM_LDS_DOUBLES];
+  const int64_t b = blockIdx.x;
+  if (b < a.npack) {
+    pack_a_block(a.pack, b % a.npack_x, (int)(b / a.npack_x));
+    return;
   }
-  __syncthreads();
-  double acc = 0.0;
-#pragma unroll 16
-  for (int ii = 0; ii < 128; ++ii) acc = fma(sj[ii][tx], sk[ii][ty], acc);
-  const int j = j0 + tx, k = k0 + ty;
-  const int64_t rr = (int64_t)a.r * a.r;
-  if (j < a.r && k < a.r) a.Bpart[((int64_t)split * a.ng + grp) * rr + (int64_t)k * a.r + j] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_gram_fin(GramFinArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t rr = a.rr;
-  if (e >= rr) return;
-  double b = 0.0;
-  for (int s = 0; s < a.nsplit; ++s) b += a.Bpart[s * rr + e];
-  a.B[e] = b;
-  a.C[e] = ipow(b, a.d - 1);
+  gram_tile(a.gram, b - a.npack, lds);
 }
 
 // ---------------------------------------------------------------------------
-// ymodel: Y_M = A D_lambda C (n x r, fp64, leading dimension n).  Block:
-// 64 rows x 16 columns, 4 outputs per thread, k in slices of 32 through LDS.
+// final: the closing step of an evaluation in one launch of 1024-thread
+// blocks, each kind of block needing about one round trip to memory.
+//   blocks [0, ntile): a 64 x 8 tile of G_A = -2d (Y - Y_M) D_lambda, one
+//     element per thread, with Y the fixed-order sum of the second product's
+//     partials (their loads issued first) and Y_M = A D_lambda C computed in
+//     place from LDS copies of up to FINAL_K columns of A D_lambda and rows
+//     of C at a time;
+//   blocks [ntile, ntile + ng r): column J: g_lambda[J] = -2 (w_J - u_J)
+//     with w_J the sum of the first product's column partials and
+//     u_J = sum_k B_kJ C_kJ lambda_k, and J's share lambda_J (u_J - 2 w_J)
+//     of f; the last column block of a model to arrive (an arrival counter
+//     per model, back at zero after every launch) adds alpha and the shares
+//     in column order into that model's f.  The shares move between blocks
+//     through device-coherent accesses.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_ymodel(YModelArgs<T> a) {
-  __shared__ double sa[32][65];   // A D_lambda slice: [k][row]
-  __shared__ double sc[32][17];   // C slice: [k][col]
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int grp = blockIdx.y / a.rt;
-  const int j0 = (blockIdx.y % a.rt) * 16;
-  const T* Ag = a.A + (int64_t)grp * a.r * a.lda;
-  const double* lg = a.lambda + (int64_t)grp * a.r;
-  const double* Cg = a.C + (int64_t)grp * a.r * a.r;
-  const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;   // row, column quarter
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < a.r; k0 += 32) {
-    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-      const int ii = e & 63, kk = e >> 6;
-      const int64_t i = i0 + ii;
-      const int k = k0 + kk;
-      sa[kk][ii] = (i < a.n && k < a.r) ? (double)Ag[(int64_t)k * a.lda + i] * lg[k] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 32 * 16; e += 256) {
-      const int cc = e & 15, kk = e >> 4;
-      const int k = k0 + kk, j = j0 + cc;
-      sc[kk][cc] = (k < a.r && j < a.r) ? Cg[(int64_t)j * a.r + k] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < 32; ++kk) {
-      const double x = sa[kk][tr];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = fma(x, sc[kk][tc * 4 + q], acc[q]);
-    }
-    __syncthreads();
-  }
-  const int64_t i = i0 + tr;
-  if (i < a.n) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + tc * 4 + q;
-      if (j < a.r) a.YM[((int64_t)grp * a.r + j) * a.n + i] = acc[q];
-    }
-  }
-}
+constexpr int FINAL_PF = 32;    // partials of Y whose loads are issued before Y_M is computed
+constexpr int FINAL_K = 128;    // k values of A D_lambda and C staged in LDS at once
 
-// ---------------------------------------------------------------------------
-// final_s: one block per column j: w_j, u_j, g_lambda[j], and j's share of f
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum_256(double v, double* sm) {
+__device__ __forceinline__ double block_sum(double v, double* sm) {
   sm[threadIdx.x] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = FINAL_THREADS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
     __syncthreads();
   }
@@ -580,57 +523,119 @@ __device__ __forceinline__ double block_sum_256(double v, double* sm) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_final_s(FinalSArgs a) {
-  __shared__ double sm[256];
-  const int j = blockIdx.x;                 // column over all models
-  const int grp = j / a.r, jl = j - grp * a.r;
+// Y_M[i0 + tr][j0 + tc] of model grp (tr = thread % 64, tc = thread / 64 <
+// FINAL_COLS), fp64, k ascending
+template <typename T>
+__device__ __forceinline__ double ymodel_elem(const T* A, int64_t lda, int n, int r, int grp, const double* lambda,
+                                              const double* C, int64_t i0, int j0, double (*sa)[65],
+                                              double (*sc)[FINAL_COLS + 1]) {
+  const T* Ag = A + (int64_t)grp * r * lda;
+  const double* lg = lambda + (int64_t)grp * r;
+  const double* Cg = C + (int64_t)grp * r * r;
+  const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < r; k0 += FINAL_K) {
+    const int kn = min(FINAL_K, r - k0);
+    for (int e = threadIdx.x; e < kn * 64; e += FINAL_THREADS) {
+      const int ii = e & 63, kk = e >> 6;
+      const int64_t i = i0 + ii;
+      const int k = k0 + kk;
+      const int64_t ic = i < n ? i : 0;
+      const double x = (double)Ag[(int64_t)k * lda + ic] * lg[k];
+      sa[kk][ii] = i < n ? x : 0.0;
+    }
+    for (int e = threadIdx.x; e < kn * FINAL_COLS; e += FINAL_THREADS) {
+      const int cc = e % FINAL_COLS, kk = e / FINAL_COLS;
+      const int k = k0 + kk, j = j0 + cc;
+      const double x = Cg[(int64_t)(j < r ? j : 0) * r + k];
+      sc[kk][cc] = j < r ? x : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kn; ++kk) acc = fma(sa[kk][tr], sc[kk][tc], acc);
+    __syncthreads();
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ double sum8(const T* v) {
+  return (((double)v[0] + (double)v[1]) + ((double)v[2] + (double)v[3])) +
+         (((double)v[4] + (double)v[5]) + ((double)v[6] + (double)v[7]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(FINAL_THREADS) void k_final(FinalArgs<T> a) {
+  __shared__ double sa[FINAL_K][65];
+  __shared__ double sc[FINAL_K][FINAL_COLS + 1];
+  __shared__ double sm[FINAL_THREADS];
+  const int64_t b = blockIdx.x;
+  const int64_t ncol = (int64_t)a.ng * a.r;
+  if (b < a.ntile) {
+    const int64_t nrb = (a.n + 63) / 64;
+    const int64_t i0 = (b % nrb) * 64;
+    const int64_t z = b / nrb;
+    const int j0 = (int)(z % a.ct) * FINAL_COLS, grp = (int)(z / a.ct);
+    const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
+    const int64_t i = i0 + tr;
+    const int j = j0 + tc;
+    const bool live = i < a.n && j < a.r;
+    const int64_t J = (int64_t)grp * a.r + j;
+    const int64_t stride = a.rp * a.npad;
+    const T* yp = a.Ypart + (live ? J * a.npad + i : 0);
+    // Y = the partials summed in groups of eight (pairwise within a group),
+    // then the remaining ones in order; the first groups' loads go out now
+    const int npf = min(a.nsplit, FINAL_PF) & ~7;
+    T yv[FINAL_PF];
+#pragma unroll
+    for (int s = 0; s < FINAL_PF; ++s) yv[s] = s < npf ? yp[s * stride] : T(0);
+    const double ym = ymodel_elem(a.A, a.lda, a.n, a.r, grp, a.lambda, a.C, i0, j0, sa, sc);
+    if (!live) return;
+    double y = 0.0;
+#pragma unroll
+    for (int s = 0; s < FINAL_PF; s += 8)
+      if (s < npf) y += sum8(yv + s);
+    int s = npf;
+    for (; s + 8 <= a.nsplit; s += 8) {
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = yp[(s + q) * stride];
+      y += sum8(v);
+    }
+    for (; s < a.nsplit; ++s) y += (double)yp[s * stride];
+    a.G[J * a.ldg + i] = (T)(-2.0 * a.d * (a.yscale * y - ym) * a.lambda[J]);
+    return;
+  }
+  // column J; the last column block of a model to arrive adds its f
+  const int J = (int)(b - a.ntile);
+  const int grp = J / a.r, jl = J - grp * a.r;
   const int64_t rr = (int64_t)a.r * a.r;
   const double* Bg = a.B + grp * rr;
   const double* Cg = a.C + grp * rr;
   const double* lg = a.lambda + (int64_t)grp * a.r;
-  double w = 0.0;
-  for (int64_t b = threadIdx.x; b < a.nwpart; b += 256) w += a.wpart[b * a.rp + j];
-  w = block_sum_256(w, sm);
-  double u = 0.0;
-  for (int k = threadIdx.x; k < a.r; k += 256)
+  double w = 0.0, u = 0.0;
+  for (int64_t q = threadIdx.x; q < a.nwpart; q += FINAL_THREADS) w += a.wpart[q * a.rp + J];
+  for (int k = threadIdx.x; k < a.r; k += FINAL_THREADS)
     u += Bg[(int64_t)k * a.r + jl] * Cg[(int64_t)k * a.r + jl] * lg[k];
-  u = block_sum_256(u, sm);
+  w = block_sum(w, sm);
+  u = block_sum(u, sm);
+  __shared__ int sflag;
   if (threadIdx.x == 0) {
-    a.g_lambda[j] = -2.0 * (w - u);
-    a.fpart[j] = a.lambda[j] * u - 2.0 * w * a.lambda[j];
+    a.g_lambda[J] = -2.0 * (w - u);
+    xput64(a.fpart + J, __builtin_bit_cast(uint64_t, a.lambda[J] * u - 2.0 * w * a.lambda[J]));
+    xput_complete();
+    sflag = __hip_atomic_fetch_add(a.count + grp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-}
-
-// one block per model
-__global__ __launch_bounds__(256) void k_final_f(FinalSArgs a) {
-  __shared__ double sm[256];
-  const int grp = blockIdx.x;
+  __syncthreads();
+  if (sflag != a.r - 1) return;                            // not the model's last column (block-uniform)
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   double s = 0.0;
-  for (int j = threadIdx.x; j < a.r; j += 256) s += a.fpart[(int64_t)grp * a.r + j];
-  s = block_sum_256(s, sm);
-  if (threadIdx.x == 0) a.f[grp] = a.alpha + s;
-}
-
-// ---------------------------------------------------------------------------
-// final_G: G_A = -2d (Y - Y_M) D_lambda, Y = fixed-order sum of the partials
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_final_G(FinalGArgs<T> a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= a.n) return;
-  const T* yp = a.Ypart + (int64_t)j * a.npad + i;
-  const int64_t stride = a.rp * a.npad;
-  double y = 0.0;
-  int s = 0;
-  for (; s + 4 <= a.nsplit; s += 4) {
-    const double y0 = (double)yp[(s + 0) * stride], y1 = (double)yp[(s + 1) * stride];
-    const double y2 = (double)yp[(s + 2) * stride], y3 = (double)yp[(s + 3) * stride];
-    y += (y0 + y1) + (y2 + y3);
+  for (int j = threadIdx.x; j < a.r; j += FINAL_THREADS)
+    s += __builtin_bit_cast(double, xget64(a.fpart + (int64_t)grp * a.r + j));
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) {
+    a.f[grp] = a.alpha + s;
+    __hip_atomic_store(a.count + grp, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  for (; s < a.nsplit; ++s) y += (double)yp[s * stride];
-  const double gval = -2.0 * a.d * (a.yscale * y - a.YM[(int64_t)j * a.n + i]) * a.lambda[j];
-  a.G[(int64_t)j * a.ldg + i] = (T)gval;
 }
 
 // ---------------------------------------------------------------------------
@@ -695,38 +700,18 @@ void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<doub
     default: break;
   }
 }
-void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<float>& a) {
-  hipLaunchKernelGGL(k_pack_a<float>, grid, dim3(256), 0, st, a);
+void launch_prep(int64_t blocks, hipStream_t st, const PrepArgs<float>& a) {
+  hipLaunchKernelGGL(k_prep<float>, dim3((unsigned)blocks), dim3(GRAM_THREADS), 0, st, a);
 }
-void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<double>& a) {
-  hipLaunchKernelGGL(k_pack_a<double>, grid, dim3(256), 0, st, a);
+void launch_prep(int64_t blocks, hipStream_t st, const PrepArgs<double>& a) {
+  hipLaunchKernelGGL(k_prep<double>, dim3((unsigned)blocks), dim3(GRAM_THREADS), 0, st, a);
 }
-void launch_gram(dim3 grid, hipStream_t st, const GramArgs<float>& a) {
-  hipLaunchKernelGGL(k_gram_part<float>, grid, dim3(256), 0, st, a);
+void launch_final(hipStream_t st, const FinalArgs<float>& a) {
+  const int64_t blocks = a.ntile + (int64_t)a.ng * a.r;
+  hipLaunchKernelGGL(k_final<float>, dim3((unsigned)blocks), dim3(FINAL_THREADS), 0, st, a);
 }
-void launch_gram(dim3 grid, hipStream_t st, const GramArgs<double>& a) {
-  hipLaunchKernelGGL(k_gram_part<double>, grid, dim3(256), 0, st, a);
+void launch_final(hipStream_t st, const FinalArgs<double>& a) {
+  const int64_t blocks = a.ntile + (int64_t)a.ng * a.r;
+  hipLaunchKernelGGL(k_final<double>, dim3((unsigned)blocks), dim3(FINAL_THREADS), 0, st, a);
 }
-void launch_gram_fin(dim3 grid, hipStream_t st, const GramFinArgs& a) {
-  hipLaunchKernelGGL(k_gram_fin, grid, dim3(256), 0, st, a);
-}
-void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<float>& a) {
-  hipLaunchKernelGGL(k_ymodel<float>, grid, dim3(256), 0, st, a);
-}
-void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<double>& a) {
-  hipLaunchKernelGGL(k_ymodel<double>, grid, dim3(256), 0, st, a);
-}
-void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<float>& a) {
-  hipLaunchKernelGGL(k_final_G<float>, grid, dim3(256), 0, st, a);
-}
-void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<double>& a) {
-  hipLaunchKernelGGL(k_final_G<double>, grid, dim3(256), 0, st, a);
-}
-void launch_final_s(dim3 grid, hipStream_t st, const FinalSArgs& a) {
-  hipLaunchKernelGGL(k_final_s, grid, dim3(256), 0, st, a);
-}
-void launch_final_f(dim3 grid, hipStream_t st, const FinalSArgs& a) {
-  hipLaunchKernelGGL(k_final_f, grid, dim3(256), 0, st, a);
-}
-
 }  // namespace symtd

@@ -82,36 +82,40 @@ template <typename T> constexpr int g1_chunk() { return G1_RUN / (int)sizeof(T);
 template <typename T>
 struct GramArgs {
   const T* A; int64_t lda; int n; int r; int ng;
-  double* Bpart;      // [ceil(n/128)][ng][r][r]
+  int rt;             // ceil(r / 16) tiles per side
+  int d;
+  double* B; double* C;   // ng blocks of r x r, column-major: B = A'A, C = B^(d-1)
 };
 
-struct GramFinArgs {
-  const double* Bpart; int nsplit; int64_t rr; int d;   // rr = ng * r * r
-  double* B; double* C;  // ng blocks of r x r, column-major
-};
-
+// The closing step of an evaluation (k_final, FINAL_THREADS-thread blocks):
+// G tiles of 64 rows x FINAL_COLS columns (the model term A D_lambda C
+// computed in place), then one block per column for w, u, g_lambda and the
+// column's share of f; the last column block of each model to finish adds f.
+constexpr int FINAL_THREADS = 512;
+constexpr int FINAL_COLS = FINAL_THREADS / 64;
 template <typename T>
-struct YModelArgs {
-  const T* A; int64_t lda; int n; int r; int ng; int rt;   // rt = ceil(r / 16)
-  const double* lambda; const double* C;
-  double* YM;         // n x (ng r), leading dimension n
-};
-
-template <typename T>
-struct FinalGArgs {
-  const T* Ypart; int64_t npad; int64_t rp; int nsplit;
-  const double* YM; int n; int r; int d;
-  const double* lambda;
+struct FinalArgs {
+  const T* Ypart; int64_t npad; int64_t rp; int nsplit; double yscale;
+  const T* A; int64_t lda; int n; int r; int ng;
+  int ct;                                // ceil(r / FINAL_COLS) column tiles per model
+  const double* lambda; const double* B; const double* C; int d;
+  const double* wpart; int64_t nwpart;   // rows of rp column partials of w
+  double alpha;
   T* G; int64_t ldg;
-  double yscale;      // Y = yscale * (sum of the partials)
+  double* fpart; double* f; double* g_lambda;   // fpart: ng r shares of f
+  int* count;                            // ng arrival counters, zero between launches
+  int64_t ntile;                         // G tile blocks: ceil(n / 64) ct ng
 };
 
-struct FinalSArgs {
-  const double* wpart; int64_t nwpart; int64_t rp;
-  const double* B; const double* C; const double* lambda;
-  int r; int ng; double alpha;
-  double* fpart;      // ng r per-column shares of f
-  double* f; double* g_lambda;   // f: ng values
+// Threads of a prep block (16 waves; a Gram tile per block).
+constexpr int GRAM_THREADS = 1024;
+
+// pack_a and the Gram tiles in one launch: blocks [0, npack) pack (npack_x
+// blocks of GRAM_THREADS elements per column), then rt rt ng Gram tiles
+template <typename T>
+struct PrepArgs {
+  PackAArgs<T> pack; int npack_x; int64_t npack;
+  GramArgs<T> gram;
 };
 
 template <typename S>
@@ -129,17 +133,10 @@ void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<floa
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<double>& a);
 void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a);
 void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<double>& a);
-void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<float>& a);
-void launch_pack_a(dim3 grid, hipStream_t st, const PackAArgs<double>& a);
-void launch_gram(dim3 grid, hipStream_t st, const GramArgs<float>& a);
-void launch_gram(dim3 grid, hipStream_t st, const GramArgs<double>& a);
-void launch_gram_fin(dim3 grid, hipStream_t st, const GramFinArgs& a);
-void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<float>& a);
-void launch_ymodel(dim3 grid, hipStream_t st, const YModelArgs<double>& a);
-void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<float>& a);
-void launch_final_G(dim3 grid, hipStream_t st, const FinalGArgs<double>& a);
-void launch_final_s(dim3 grid, hipStream_t st, const FinalSArgs& a);
-void launch_final_f(dim3 grid, hipStream_t st, const FinalSArgs& a);
+void launch_prep(int64_t blocks, hipStream_t st, const PrepArgs<float>& a);
+void launch_prep(int64_t blocks, hipStream_t st, const PrepArgs<double>& a);
+void launch_final(hipStream_t st, const FinalArgs<float>& a);
+void launch_final(hipStream_t st, const FinalArgs<double>& a);
 
 void launch_widen(hipStream_t st, const float* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                   int64_t cols);

@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels.hpp"
+
 namespace symtd {
 
 enum LpKind { LP_F16 = 0, LP_BF16X3 = 1 };
@@ -93,7 +95,8 @@ struct LpConvArgs {
 
 void launch_lp_gemm1(int kind, int nt, dim3 grid, hipStream_t st, const LpG1Args& a);
 void launch_lp_gemm2(int kind, int nt, dim3 grid, hipStream_t st, const LpG2Args& a);
-void launch_lp_pack_a(int kind, hipStream_t st, const LpPackArgs& a);
+// the 16-bit copy of A and gram_blocks Gram tiles (model_dev.hpp) in one launch
+void launch_lp_prep(int kind, int64_t gram_blocks, hipStream_t st, const LpPackArgs& a, const GramArgs<float>& g);
 void launch_lp_convert(int kind, hipStream_t st, const LpConvArgs& a);
 void launch_max_abs(hipStream_t st, const double* x, int64_t count, double* out);
 

@@ -14,6 +14,7 @@
 
 #include "kcommon.hpp"
 #include "lp.hpp"
+#include "model_dev.hpp"
 
 namespace symtd {
 
@@ -428,11 +429,12 @@ __global__ __launch_bounds__(256) void k_lp_gemm2(LpG2Args a) {
 // conversions
 // ---------------------------------------------------------------------------
 template <int KIND>
-__global__ __launch_bounds__(256) void k_lp_pack_a(LpPackArgs a) {
+__device__ __forceinline__ void lp_pack_a_blocks(const LpPackArgs& a, int64_t b, int64_t nb) {
   using E = typename LpT<KIND>::E;
   constexpr int PL = LpT<KIND>::PLANES;
   const int64_t total = (int64_t)a.rp * a.kc_len;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+  const int64_t bs = blockDim.x;
+  for (int64_t e = b * bs + threadIdx.x; e < total; e += nb * bs) {
     const int64_t j = e / a.kc_len, k = e - j * a.kc_len;
     const double x = (k < a.n && j < a.r) ? (double)a.A[j * a.lda + k] : 0.0;
     E parts[PL];
@@ -440,6 +442,19 @@ __global__ __launch_bounds__(256) void k_lp_pack_a(LpPackArgs a) {
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) ((E*)a.Ac)[pl * a.aplane + j * a.ldc + k] = parts[pl];
   }
+}
+
+// the 16-bit copy of A and the Gram tiles of the fp32 A in one launch:
+// blocks [0, npack) convert, the rest are Gram tiles
+template <int KIND>
+__global__ __launch_bounds__(GRAM_THREADS) void k_lp_prep(LpPackArgs pk, int64_t npack, GramArgs<float> gram) {
+  __shared__ double lds[GRAM_LDS_DOUBLES];
+  const int64_t b = blockIdx.x;
+  if (b < npack) {
+    lp_pack_a_blocks<KIND>(pk, b, npack);
+    return;
+  }
+  gram_tile(gram, b - npack, lds);
 }
 
 // Vc (column-major, ld ldc) elementwise; Vr (row-major, ld ldr) through
@@ -535,11 +550,12 @@ void launch_lp_gemm2(int kind, int nt, dim3 grid, hipStream_t st, const LpG2Args
   if (kind == LP_F16) g2<LP_F16>(nt, grid, st, a);
   else g2<LP_BF16X3>(nt, grid, st, a);
 }
-void launch_lp_pack_a(int kind, hipStream_t st, const LpPackArgs& a) {
+void launch_lp_prep(int kind, int64_t gram_blocks, hipStream_t st, const LpPackArgs& a, const GramArgs<float>& g) {
   const int64_t total = (int64_t)a.rp * a.kc_len;
-  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
-  if (kind == LP_F16) hipLaunchKernelGGL(k_lp_pack_a<LP_F16>, dim3(blocks), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(k_lp_pack_a<LP_BF16X3>, dim3(blocks), dim3(256), 0, st, a);
+  const int64_t npack = std::min<int64_t>((total + GRAM_THREADS - 1) / GRAM_THREADS, 1024);
+  const dim3 grid((unsigned)(npack + gram_blocks));
+  if (kind == LP_F16) hipLaunchKernelGGL(k_lp_prep<LP_F16>, grid, dim3(GRAM_THREADS), 0, st, a, npack, g);
+  else hipLaunchKernelGGL(k_lp_prep<LP_BF16X3>, grid, dim3(GRAM_THREADS), 0, st, a, npack, g);
 }
 void launch_lp_convert(int kind, hipStream_t st, const LpConvArgs& a) {
   const int64_t total = (int64_t)a.p * a.kc_len;

@@ -11,12 +11,13 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "model_dev.hpp"
 #include "lbfgs.hpp"
 #include "runtime.hpp"
 
 using namespace symtd;
 
-static const char* kProfileNames[] = {"gemm1", "gemm2", "model", "final_G", "scalars", "normx", "reduce"};
+static const char* kProfileNames[] = {"gemm1", "gemm2", "prep", "final", "normx", "reduce"};
 static constexpr int kNumProfile = sizeof(kProfileNames) / sizeof(kProfileNames[0]);
 
 symtd_status symtd_ctx::fail(symtd_status s, const char* fmt, ...) {
@@ -68,19 +69,35 @@ symtd_status symtd_ctx::reserve_solver(size_t bytes) {
   return SYMTD_OK;
 }
 
-void symtd_ctx::prof_begin(int which, hipStream_t st) {
-  if (!prof) return;
-  hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess) return;
-  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
-  (void)hipEventRecord(a, st);
-  pending.push_back({which, a, b, st});
+hipEvent_t symtd_ctx::pool_event() {
+  if (!ev_pool.empty()) {
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
 }
 
-void symtd_ctx::prof_end(hipStream_t st) {
-  if (!prof || pending.empty()) return;
+void symtd_ctx::prof_begin(int which, hipStream_t st) {
+  if (!((prof_mask >> which) & 1u)) return;
+  hipEvent_t a = pool_event(), b = pool_event();
+  if (!a || !b) {
+    if (a) ev_pool.push_back(a);
+    if (b) ev_pool.push_back(b);
+    return;
+  }
+  (void)hipEventRecord(a, st);
+  pending.push_back({which, a, b});
+}
+
+void symtd_ctx::prof_end(int which, hipStream_t st) {
+  if (!((prof_mask >> which) & 1u) || pending.empty() || pending.back().which != which) return;
   (void)hipEventRecord(pending.back().stop, st);
-  (void)st;
 }
 
 symtd_status symtd_ctx::set_device() {
@@ -111,10 +128,10 @@ template <typename X>
 bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct FgPlan {
-  int nt_tot, rp, nblk, nt1, nt2, nslab, nblocks, nsplit, blk_per_split, rowblocks, gsplit;
+  int nt_tot, rp, nblk, nt1, nt2, nslab, nblocks, nsplit, blk_per_split, rowblocks;
   int64_t npad;
   int64_t ldap;
-  size_t apad, wp, wpart, part, ypart, bpart, rr, ym;  // element counts
+  size_t apad, wp, wpart, part, ypart, rr, fp;  // element counts
   size_t bytes(size_t esz) const {
     size_t s = 0;
     auto add = [&](size_t b) { s = ((s + 255) & ~(size_t)255) + b; };
@@ -123,11 +140,9 @@ struct FgPlan {
     add(wpart * sizeof(double));
     add(part * esz);
     add(ypart * esz);
-    add(bpart * sizeof(double));
     add(rr * sizeof(double));
     add(rr * sizeof(double));
-    add(ym * sizeof(double));
-    add(256 * sizeof(double));
+    add(fp * sizeof(double));
     return s + 256;
   }
 };
@@ -150,7 +165,6 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   nsplit = std::min(nsplit, P.nblk);
   P.blk_per_split = (P.nblk + nsplit - 1) / nsplit;
   P.nsplit = (P.nblk + P.blk_per_split - 1) / P.blk_per_split;
-  P.gsplit = (int)((n + 127) / 128);
   const int kch = f64 ? g1_chunk<double>() : g1_chunk<float>();
   P.ldap = ((n + kch - 1) / kch) * kch;
   P.apad = (size_t)P.rp * P.ldap;
@@ -158,9 +172,8 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   P.wpart = (size_t)G1_WAVES * P.nblocks * P.rp;
   P.part = (size_t)P.nblocks * G1_WAVES * G1_MT * P.nt1 * 256;
   P.ypart = (size_t)P.nsplit * P.rp * P.npad;
-  P.bpart = (size_t)P.gsplit * r * r;
   P.rr = (size_t)r * r;
-  P.ym = (size_t)n * r;
+  P.fp = (size_t)r;
   return P;
 }
 
@@ -176,8 +189,7 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   const int64_t r1 = r;            // columns of one model
   r = r1 * ng;                     // columns of all models (the products see them all)
   FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count, ctx->tune_g1_blocks, ctx->tune_g2_splits);
-  P.rr = (size_t)ng * r1 * r1;
-  P.bpart = (size_t)P.gsplit * P.rr;
+  P.rr = (size_t)ng * r1 * r1;      // B and C: one r1 x r1 block per model
   if (P.nblocks > ctx->nflags) return ctx->fail(SYMTD_EINVAL, "internal: %d blocks exceed the flag array", P.nblocks);
   symtd_status s = ctx->reserve(P.bytes(sizeof(T)));
   if (s != SYMTD_OK) return s;
@@ -187,36 +199,26 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   double* wpart = cv.take<double>(P.wpart);
   T* part = cv.take<T>(P.part);
   T* Ypart = cv.take<T>(P.ypart);
-  double* Bpart = cv.take<double>(P.bpart);
   double* B = cv.take<double>(P.rr);
   double* C = cv.take<double>(P.rr);
-  double* YM = cv.take<double>(P.ym);
-  double* fpart = cv.take<double>(r);
+  double* fpart = cv.take<double>(P.fp);
 
   const size_t vq = 16 / sizeof(T);
   const bool vecV = aligned_to<T>(V, 16) && (ldv % vq) == 0;
-  // the model terms (B, C, Y_M) and the scalars run on the side stream beside
-  // gemm1/gemm2 (fork/join through events), or in order on the caller's stream
-  hipStream_t side = ctx->tune_serial ? st : ctx->side;
+  const int rt = (int)((r1 + 15) / 16);
+  if (ng > symtd_ctx::kFinalCounters)
+    return ctx->fail(SYMTD_EINVAL, "%d models side by side exceed the %d supported", ng, symtd_ctx::kFinalCounters);
+  // four launches on the caller's stream: prep, gemm1, gemm2, final
 
-  (void)hipEventRecord(ctx->ev_fork, st);
-  (void)hipStreamWaitEvent(side, ctx->ev_fork, 0);
-  {
-    GramArgs<T> ga{A, lda, (int)n, (int)r1, ng, Bpart};
-    const unsigned rt = (unsigned)((r1 + 15) / 16);
-    ctx->prof_begin(2, side);
-    launch_gram(dim3(rt, rt, (unsigned)(P.gsplit * ng)), side, ga);
-    GramFinArgs gf{Bpart, P.gsplit, (int64_t)P.rr, d, B, C};
-    launch_gram_fin(dim3((unsigned)((P.rr + 255) / 256)), side, gf);
-    YModelArgs<T> ya{A, lda, (int)n, (int)r1, ng, (int)rt, lambda, C, YM};
-    launch_ymodel(dim3((unsigned)((n + 63) / 64), rt * (unsigned)ng), side, ya);
-    ctx->prof_end(side);
-    (void)hipEventRecord(ctx->ev_model, side);
-  }
-  // zero-padded factor copy for gemm1
+  // prep: zero-padded factor copy for gemm1, and B = A'A, C = B^{d-1}
   {
     PackAArgs<T> pa{A, lda, (int)n, (int)r, Apad, P.ldap};
-    launch_pack_a(dim3((unsigned)((P.ldap + 255) / 256), (unsigned)P.rp), st, pa);
+    GramArgs<T> ga{A, lda, (int)n, (int)r1, ng, rt, d, B, C};
+    const int npack_x = (int)((P.ldap + GRAM_THREADS - 1) / GRAM_THREADS);
+    const int64_t npack = (int64_t)npack_x * P.rp;
+    ctx->prof_begin(2, st);
+    launch_prep(npack + (int64_t)rt * rt * ng, st, PrepArgs<T>{pa, npack_x, npack, ga});
+    ctx->prof_end(2, st);
   }
   // Z = V'A and its epilogue, one launch per column group; the direct
   // global-to-LDS path needs 16-byte aligned columns holding whole quads
@@ -227,18 +229,7 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
                  P.nslab, P.nblocks, d, Apad, P.ldap, Wp, wpart, part, ctx->flags, ctx->dev_err};
     ctx->prof_begin(0, st);
     launch_gemm1(nt, dma, dim3(P.nblocks), st, a1);
-    ctx->prof_end(st);
-  }
-  // w, u, f, g_lambda on the side stream once gemm1 is done
-  (void)hipEventRecord(ctx->ev_g1, st);
-  (void)hipStreamWaitEvent(side, ctx->ev_g1, 0);
-  {
-    FinalSArgs as{wpart, (int64_t)G1_WAVES * P.nblocks, P.rp, B, C, lambda, (int)r1, ng, alpha, fpart, f, g_lambda};
-    ctx->prof_begin(4, side);
-    launch_final_s(dim3((unsigned)r), side, as);
-    launch_final_f(dim3((unsigned)ng), side, as);
-    ctx->prof_end(side);
-    (void)hipEventRecord(ctx->ev_side, side);
+    ctx->prof_end(0, st);
   }
   // Y = V W, split over the observations
   for (int t0 = 0; t0 < P.nt_tot; t0 += P.nt2) {
@@ -248,18 +239,19 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
     const unsigned blocks = (unsigned)(P.rowblocks * 8 * ((P.nsplit + 7) / 8));
     ctx->prof_begin(1, st);
     launch_gemm2(nt, vecV && (n % 4) == 0, dim3(blocks), st, a2);
-    ctx->prof_end(st);
+    ctx->prof_end(1, st);
   }
-  (void)hipStreamWaitEvent(st, ctx->ev_model, 0);
+  // G_A, w, u, g_lambda, f
+  ctx->prof_begin(3, st);
   {
-    FinalGArgs<T> ag{Ypart, P.npad, P.rp, P.nsplit, YM, (int)n, (int)r, d, lambda, G, ldg, 1.0};
-    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)r);
-    ctx->prof_begin(3, st);
-    launch_final_G(grid, st, ag);
-    ctx->prof_end(st);
+    const int ct = (int)((r1 + FINAL_COLS - 1) / FINAL_COLS);
+    const int64_t ntile = ((n + 63) / 64) * ct * ng;
+    FinalArgs<T> fa{Ypart, P.npad, P.rp, P.nsplit, 1.0, A, lda, (int)n, (int)r1, ng, ct, lambda, B, C, d,
+                    wpart, (int64_t)G1_WAVES * P.nblocks, alpha, G, ldg, fpart, f, g_lambda, ctx->final_count,
+                    ntile};
+    launch_final(st, fa);
   }
-  // join
-  (void)hipStreamWaitEvent(st, ctx->ev_side, 0);
+  ctx->prof_end(3, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ctx->hip_fail(e, "kernel launch (fg)");
   return SYMTD_OK;
@@ -366,13 +358,13 @@ symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, 
   const size_t vq = 16 / sizeof(S);
   const bool vec = aligned_to<S>(V, 16) && (ldv % vq) == 0;
   NormXArgs<S> a{V, ldv, nu, (int)n, (int)p, d, T, part};
-  ctx->prof_begin(5, st);
+  ctx->prof_begin(4, st);
   launch_normx(vec, dim3((unsigned)pairs), st, a);
-  ctx->prof_end(st);
+  ctx->prof_end(4, st);
   ReduceArgs ra{part, pairs, alpha};
-  ctx->prof_begin(6, st);
+  ctx->prof_begin(5, st);
   launch_reduce(st, ra);
-  ctx->prof_end(st);
+  ctx->prof_end(5, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ctx->hip_fail(e, "kernel launch (normX)");
   return SYMTD_OK;
@@ -437,20 +429,17 @@ symtd_status symtd_create(int device, symtd_ctx** out) {
   if (!c) return SYMTD_ENOMEM;
   c->device = device;
   c->cu_count = prop.multiProcessorCount;
-  if (hipSetDevice(device) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_model, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_g1, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc(&c->flags, sizeof(int) * (4 * (size_t)c->cu_count + 1)) != hipSuccess ||
-      hipMemset(c->flags, 0, sizeof(int) * (4 * (size_t)c->cu_count + 1)) != hipSuccess) {
+  // flags, the error word and the arrival counters in one zeroed allocation
+  const size_t words = 4 * (size_t)c->cu_count + 1 + symtd_ctx::kFinalCounters;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->flags, sizeof(int) * words) != hipSuccess ||
+      hipMemset(c->flags, 0, sizeof(int) * words) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     symtd_destroy(c);
     return SYMTD_EDEVICE;
   }
   c->nflags = 4 * c->cu_count;  // >= the blocks of any split product
   c->dev_err = c->flags + c->nflags;
+  c->final_count = c->dev_err + 1;
   *out = c;
   return SYMTD_OK;
 }
@@ -460,9 +449,7 @@ void symtd_destroy(symtd_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (auto& pe : ctx->pending) { (void)hipEventDestroy(pe.start); (void)hipEventDestroy(pe.stop); }
-  for (hipEvent_t ev : {ctx->ev_fork, ctx->ev_model, ctx->ev_g1, ctx->ev_side})
-    if (ev) (void)hipEventDestroy(ev);
-  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  for (hipEvent_t ev : ctx->ev_pool) (void)hipEventDestroy(ev);
   if (ctx->flags) (void)hipFree(ctx->flags);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->sws) (void)hipFree(ctx->sws);
@@ -532,15 +519,14 @@ symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value)
   switch (key) {
     case SYMTD_TUNE_G1_BLOCKS: ctx->tune_g1_blocks = value; return SYMTD_OK;
     case SYMTD_TUNE_G2_SPLITS: ctx->tune_g2_splits = value; return SYMTD_OK;
-    case SYMTD_TUNE_SERIAL: ctx->tune_serial = value; return SYMTD_OK;
     case SYMTD_TUNE_GRAPH: ctx->tune_graph = value; return SYMTD_OK;
   }
   return ctx->fail(SYMTD_EINVAL, "unknown tuning key %d", (int)key);
 }
 
-symtd_status symtd_profile_enable(symtd_ctx* ctx, int enable) {
+symtd_status symtd_profile_enable(symtd_ctx* ctx, uint32_t mask) {
   if (!ctx) return SYMTD_EINVAL;
-  ctx->prof = enable != 0;
+  ctx->prof_mask = mask;
   return SYMTD_OK;
 }
 
@@ -548,8 +534,8 @@ symtd_status symtd_profile_reset(symtd_ctx* ctx) {
   if (!ctx) return SYMTD_EINVAL;
   for (auto& pe : ctx->pending) {
     (void)hipEventSynchronize(pe.stop);
-    (void)hipEventDestroy(pe.start);
-    (void)hipEventDestroy(pe.stop);
+    ctx->ev_pool.push_back(pe.start);
+    ctx->ev_pool.push_back(pe.stop);
   }
   ctx->pending.clear();
   return SYMTD_OK;

@@ -20,22 +20,24 @@ struct symtd_ctx {
   size_t wide_bytes = 0;
   int* host_flag = nullptr;   // pinned host word for polling the solver's stop count
   double fwide_host = 0.0;    // host landing of the final fp64 evaluation
-  // side stream for the model terms, and the events of the fork/join
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_model = nullptr, ev_g1 = nullptr, ev_side = nullptr;
-  // hand-off flags of the split products (zero between launches) and a
-  // device error word set if a hand-off wait ever gives up
+  // hand-off flags of the split products (zero between launches), a device
+  // error word set if a hand-off wait ever gives up, and the arrival
+  // counters of the closing step, one per model (zero between launches)
   int* flags = nullptr;
   int nflags = 0;
   int* dev_err = nullptr;
+  int* final_count = nullptr;
+  static constexpr int kFinalCounters = 1024;
   // work-split overrides (0 = automatic)
-  int64_t tune_g1_blocks = 0, tune_g2_splits = 0, tune_serial = 0;
+  int64_t tune_g1_blocks = 0, tune_g2_splits = 0;
   int64_t tune_graph = 1;   // grouped engine: replay captured steps (1) or launch eagerly (0)
 
-  // per-kernel timing (symtd_profile_*)
-  struct Pending { int which; hipEvent_t start, stop; hipStream_t st; };
-  bool prof = false;
+  // per-kernel timing (symtd_profile_*): kernels whose bit is set in
+  // prof_mask are bracketed by events taken from a reusable pool
+  struct Pending { int which; hipEvent_t start, stop; };
+  uint32_t prof_mask = 0;
   std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
 
   symtd_status fail(symtd_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
   symtd_status hip_fail(hipError_t e, const char* what);
@@ -45,7 +47,8 @@ struct symtd_ctx {
   symtd_status check_common(symtd_dtype dt, const void* V, int64_t ldv, const double* nu,
                             int64_t n, int64_t p, int d);
   void prof_begin(int which, hipStream_t st);
-  void prof_end(hipStream_t st);
+  void prof_end(int which, hipStream_t st);
+  hipEvent_t pool_event();
 };
 
 namespace symtd {

@@ -148,3 +148,38 @@ def test_bad_arguments(ctx):
     assert e.value.status == -1 and "order" in str(e.value)
     with pytest.raises(S.SymtdError):
         S.symtd_fg(ctx, V, nu, A, lam, 3, prec=S.PREC_FP32)   # fp64 storage with fp32 products
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+@pytest.mark.parametrize("n,p,r,models", [(300, 20000, 40, 1), (37, 3000, 5, 3), (130, 9000, 17, 4),
+                                          (1000, 30000, 100, 1)])
+def test_alternating_inputs(ctx, kind, n, p, r, models):
+    """Two different factor sets evaluated in turn, three times each: every
+    call gives the bits of that set's first call.  The closing kernel's last
+    column block of each model writes f on an arrival counter that must be
+    back at zero after every launch; a stale f would show the other set's
+    value."""
+    d = 3
+    dt = torch.float64 if kind == "f64" else torch.float32
+    V, nu, _ = synth.gmm(n, r, p, 1e-2, 61, n)
+    V = stored(V, kind)
+    Vd, nud = to_dev(V, dt), to_dev(nu, torch.float64)
+    sets = []
+    for k in range(2):
+        A = stored(synth.gauss_factors(n, r * models, 62, n, k), kind)
+        lam = synth.gauss_factors(r * models, 1, 63, n, k)[:, 0] + 0.5
+        sets.append((to_dev(A, dt), to_dev(lam, torch.float64)))
+    print(f"case n={n} p={p} r={r} models={models} kind={kind}", flush=True)
+
+    def once(k):
+        f, g, G = S.symtd_fg_multi(ctx, Vd, nud, sets[k][0], sets[k][1], r, d, 1.5)
+        torch.cuda.synchronize()
+        return f.cpu().numpy(), g.cpu().numpy(), G.cpu().numpy()
+
+    first = [once(0), once(1)]
+    assert not np.array_equal(first[0][0], first[1][0])
+    for _ in range(3):
+        for k in range(2):
+            got = once(k)
+            for x, y in zip(got, first[k]):
+                assert np.array_equal(x, y)

@@ -83,3 +83,31 @@ def test_fp32_handle_forwards(ctx):
     torch.cuda.synchronize()
     assert all(torch.equal(x, y) for x, y in zip(a, b))
     data.close()
+
+
+@pytest.mark.parametrize("name", PRECS)
+@pytest.mark.parametrize("n,p,r", [(130, 9000, 17), (1000, 30000, 100)])
+def test_alternating_inputs(ctx, name, n, p, r):
+    """Two different factor sets evaluated in turn on one data handle: every
+    call gives the bits of that set's first call (the closing kernel's
+    arrival counter is back at zero after every launch)."""
+    V, nu, A0, lam0 = make_case(n, p, r, 3, (9, n), 1e-2, "f32")
+    _, _, A1, lam1 = make_case(n, p, r, 3, (10, n), 1e-2, "f32")
+    print(f"case n={n} p={p} r={r} prec={name}", flush=True)
+    data = S.Data(ctx, to_dev(V, torch.float32), to_dev(nu, torch.float64), prec_of(name))
+    sets = [(to_dev(A0, torch.float32), to_dev(lam0, torch.float64)),
+            (to_dev(A1, torch.float32), to_dev(lam1, torch.float64))]
+    try:
+        def once(k):
+            out = data.fg(sets[k][0], sets[k][1], 3, 2.0)
+            torch.cuda.synchronize()
+            return [x.cpu().numpy() for x in out]
+
+        first = [once(0), once(1)]
+        assert not np.array_equal(first[0][0], first[1][0])
+        for _ in range(3):
+            for k in range(2):
+                for x, y in zip(once(k), first[k]):
+                    assert np.array_equal(x, y)
+    finally:
+        data.close()

@@ -498,8 +498,8 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_prep(PrepArgs<T> a) {
 //   blocks [0, ntile): a 64 x 8 tile of G_A = -2d (Y - Y_M) D_lambda, one
 //     element per thread, with Y the fixed-order sum of the second product's
 //     partials (their loads issued first) and Y_M = A D_lambda C computed in
-//     place from LDS copies of up to FINAL_K columns of A D_lambda and rows
-//     of C at a time;
+//     place from LDS copies of up to FINAL_K columns of A and rows of
+//     D_lambda C at a time;
 //   blocks [ntile, ntile + ng r): column J: g_lambda[J] = -2 (w_J - u_J)
 //     with w_J the sum of the first product's column partials and
 //     u_J = sum_k B_kJ C_kJ lambda_k, and J's share lambda_J (u_J - 2 w_J)
@@ -508,7 +508,9 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_prep(PrepArgs<T> a) {
 //     in column order into that model's f.  The shares move between blocks
 //     through device-coherent accesses.
 // ---------------------------------------------------------------------------
-constexpr int FINAL_PF = 32;    // partials of Y whose loads are issued before Y_M is computed
+// partials of Y whose loads are issued before Y_M is computed (128 bytes of
+// registers per thread)
+template <typename T> constexpr int final_pf() { return 128 / (int)sizeof(T); }
 constexpr int FINAL_K = 128;    // k values of A D_lambda and C staged in LDS at once
 
 __device__ __forceinline__ double block_sum(double v, double* sm) {
@@ -524,37 +526,64 @@ __device__ __forceinline__ double block_sum(double v, double* sm) {
 }
 
 // Y_M[i0 + tr][j0 + tc] of model grp (tr = thread % 64, tc = thread / 64 <
-// FINAL_COLS), fp64, k ascending
+// FINAL_COLS), fp64: sum over k of A[i][k] (lambda_k C[k][j]), in four
+// interleaved partial sums (k mod 4) added at the end.  A slice of up to
+// FINAL_K values of k moves to LDS in two steps: ym_load issues every load of
+// the slice and uses none, ym_use stores the slice and multiplies it in; the
+// caller can issue its own loads in between so that they overlap.  (All
+// array indices are static, so that nothing leaves registers.)
+constexpr int YM_ITA = FINAL_K * 64 / FINAL_THREADS;
+constexpr int YM_ITC = (FINAL_K * FINAL_COLS + FINAL_THREADS - 1) / FINAL_THREADS;
+
 template <typename T>
-__device__ __forceinline__ double ymodel_elem(const T* A, int64_t lda, int n, int r, int grp, const double* lambda,
-                                              const double* C, int64_t i0, int j0, double (*sa)[65],
-                                              double (*sc)[FINAL_COLS + 1]) {
-  const T* Ag = A + (int64_t)grp * r * lda;
-  const double* lg = lambda + (int64_t)grp * r;
-  const double* Cg = C + (int64_t)grp * r * r;
-  const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
-  double acc = 0.0;
-  for (int k0 = 0; k0 < r; k0 += FINAL_K) {
-    const int kn = min(FINAL_K, r - k0);
-    for (int e = threadIdx.x; e < kn * 64; e += FINAL_THREADS) {
-      const int ii = e & 63, kk = e >> 6;
-      const int64_t i = i0 + ii;
-      const int k = k0 + kk;
-      const int64_t ic = i < n ? i : 0;
-      const double x = (double)Ag[(int64_t)k * lda + ic] * lg[k];
-      sa[kk][ii] = i < n ? x : 0.0;
-    }
-    for (int e = threadIdx.x; e < kn * FINAL_COLS; e += FINAL_THREADS) {
-      const int cc = e % FINAL_COLS, kk = e / FINAL_COLS;
-      const int k = k0 + kk, j = j0 + cc;
-      const double x = Cg[(int64_t)(j < r ? j : 0) * r + k];
-      sc[kk][cc] = j < r ? x : 0.0;
-    }
-    __syncthreads();
-    for (int kk = 0; kk < kn; ++kk) acc = fma(sa[kk][tr], sc[kk][tc], acc);
-    __syncthreads();
+__device__ __forceinline__ void ym_load(const T* Ag, int64_t lda, int n, int r, const double* lg, const double* Cg,
+                                        int64_t i0, int j0, int k0, T (&xa)[YM_ITA], double (&xc)[YM_ITC],
+                                        double (&xl)[YM_ITC]) {
+  const int kn = min(FINAL_K, r - k0);
+#pragma unroll
+  for (int it = 0; it < YM_ITA; ++it) {
+    const int e = threadIdx.x + it * FINAL_THREADS;
+    const int ii = e & 63, kk = min(e >> 6, kn - 1);
+    const int64_t i = i0 + ii;
+    xa[it] = Ag[(int64_t)(k0 + kk) * lda + (i < n ? i : 0)];
   }
-  return acc;
+#pragma unroll
+  for (int it = 0; it < YM_ITC; ++it) {
+    const int e = threadIdx.x + it * FINAL_THREADS;
+    const int cc = e % FINAL_COLS, kk = min(e / FINAL_COLS, kn - 1), j = j0 + cc;
+    xc[it] = Cg[(int64_t)(j < r ? j : 0) * r + k0 + kk];
+    xl[it] = lg[k0 + kk];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void ym_use(int n, int r, int64_t i0, int j0, int k0, const T (&xa)[YM_ITA],
+                                       const double (&xc)[YM_ITC], const double (&xl)[YM_ITC], double (*sa)[65],
+                                       double (*sc)[FINAL_COLS + 1], double (&acc)[4]) {
+  const int kn = min(FINAL_K, r - k0);
+#pragma unroll
+  for (int it = 0; it < YM_ITA; ++it) {
+    const int e = threadIdx.x + it * FINAL_THREADS;
+    const int ii = e & 63, kk = e >> 6;
+    if (kk < kn) sa[kk][ii] = i0 + ii < n ? (double)xa[it] : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < YM_ITC; ++it) {
+    const int e = threadIdx.x + it * FINAL_THREADS;
+    const int cc = e % FINAL_COLS, kk = e / FINAL_COLS;
+    if (kk < kn) sc[kk][cc] = j0 + cc < r ? xl[it] * xc[it] : 0.0;
+  }
+  __syncthreads();
+  const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
+  int kk = 0;
+  for (; kk + 4 <= kn; kk += 4) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) acc[h] = fma(sa[kk + h][tr], sc[kk + h][tc], acc[h]);
+  }
+  if (kk < kn) acc[0] = fma(sa[kk][tr], sc[kk][tc], acc[0]);
+  if (kk + 1 < kn) acc[1] = fma(sa[kk + 1][tr], sc[kk + 1][tc], acc[1]);
+  if (kk + 2 < kn) acc[2] = fma(sa[kk + 2][tr], sc[kk + 2][tc], acc[2]);
+  __syncthreads();
 }
 
 template <typename T>
@@ -584,15 +613,31 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_final(FinalArgs<T> a) {
     const T* yp = a.Ypart + (live ? J * a.npad + i : 0);
     // Y = the partials summed in groups of eight (pairwise within a group),
     // then the remaining ones in order; the first groups' loads go out now
-    const int npf = min(a.nsplit, FINAL_PF) & ~7;
-    T yv[FINAL_PF];
+    constexpr int PF = final_pf<T>();
+    const int npf = min(a.nsplit, PF) & ~7;
+    const T* Ag = a.A + (int64_t)grp * a.r * a.lda;
+    const double* lg = a.lambda + (int64_t)grp * a.r;
+    const double* Cg = a.C + (int64_t)grp * a.r * a.r;
+    T xa[YM_ITA];
+    double xc[YM_ITC], xl[YM_ITC];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    ym_load(Ag, a.lda, a.n, a.r, lg, Cg, i0, j0, 0, xa, xc, xl);
+    // the first partials of Y: unconditional loads from valid partials (a
+    // condition would make each load a branch that waits for it), issued
+    // behind the first slice of Y_M's loads; only the first npf are used
+    T yv[PF];
 #pragma unroll
-    for (int s = 0; s < FINAL_PF; ++s) yv[s] = s < npf ? yp[s * stride] : T(0);
-    const double ym = ymodel_elem(a.A, a.lda, a.n, a.r, grp, a.lambda, a.C, i0, j0, sa, sc);
+    for (int s = 0; s < PF; ++s) yv[s] = yp[(int64_t)min(s, a.nsplit - 1) * stride];
+    ym_use(a.n, a.r, i0, j0, 0, xa, xc, xl, sa, sc, acc);
+    for (int k0 = FINAL_K; k0 < a.r; k0 += FINAL_K) {
+      ym_load(Ag, a.lda, a.n, a.r, lg, Cg, i0, j0, k0, xa, xc, xl);
+      ym_use(a.n, a.r, i0, j0, k0, xa, xc, xl, sa, sc, acc);
+    }
+    const double ym = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     if (!live) return;
     double y = 0.0;
 #pragma unroll
-    for (int s = 0; s < FINAL_PF; s += 8)
+    for (int s = 0; s < PF; s += 8)
       if (s < npf) y += sum8(yv + s);
     int s = npf;
     for (; s + 8 <= a.nsplit; s += 8) {
@@ -613,7 +658,20 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_final(FinalArgs<T> a) {
   const double* Cg = a.C + grp * rr;
   const double* lg = a.lambda + (int64_t)grp * a.r;
   double w = 0.0, u = 0.0;
-  for (int64_t q = threadIdx.x; q < a.nwpart; q += FINAL_THREADS) w += a.wpart[q * a.rp + J];
+  // loads in batches of four, issued (from valid rows, without branches)
+  // before they are summed
+  for (int64_t q0 = threadIdx.x; q0 < a.nwpart; q0 += 4 * FINAL_THREADS) {
+    double v[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int64_t q = q0 + h * FINAL_THREADS;
+      v[h] = a.wpart[(q < a.nwpart ? q : q0) * a.rp + J];
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      if (q0 + h * FINAL_THREADS >= a.nwpart) v[h] = 0.0;
+    w += (v[0] + v[1]) + (v[2] + v[3]);
+  }
   for (int k = threadIdx.x; k < a.r; k += FINAL_THREADS)
     u += Bg[(int64_t)k * a.r + jl] * Cg[(int64_t)k * a.r + jl] * lg[k];
   w = block_sum(w, sm);

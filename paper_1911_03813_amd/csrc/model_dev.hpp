@@ -43,14 +43,25 @@ __device__ __forceinline__ void gram_tile(const GramArgs<T>& a, int64_t t, doubl
   const T* Ag = a.A + (int64_t)grp * a.r * a.lda;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
   for (int64_t i0 = 0; i0 < a.n; i0 += GRAM_ROWS) {
-    // panel p (0: columns j0.., 1: columns k0..), column cc, row ii
-    for (int e = threadIdx.x; e < 2 * 16 * GRAM_ROWS; e += GRAM_THREADS) {
+    // panel p (0: columns j0.., 1: columns k0..), column cc, row ii; all of
+    // a thread's loads are issued before any is used
+    constexpr int IT = 2 * 16 * GRAM_ROWS / GRAM_THREADS;
+    T x[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + it * GRAM_THREADS;
       const int ii = e % GRAM_ROWS, cc = (e / GRAM_ROWS) % 16, pnl = e / (16 * GRAM_ROWS);
       const int col = (pnl ? k0 : j0) + cc;
       const int64_t i = i0 + ii;
-      const bool ok = i < a.n && col < a.r;
-      const T x = Ag[(int64_t)(col < a.r ? col : 0) * a.lda + (i < a.n ? i : 0)];
-      lds[(pnl * 16 + cc) * GRAM_LD + ii] = ok ? (double)x : 0.0;
+      x[it] = Ag[(int64_t)(col < a.r ? col : 0) * a.lda + (i < a.n ? i : 0)];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + it * GRAM_THREADS;
+      const int ii = e % GRAM_ROWS, cc = (e / GRAM_ROWS) % 16, pnl = e / (16 * GRAM_ROWS);
+      const int col = (pnl ? k0 : j0) + cc;
+      const bool ok = i0 + ii < a.n && col < a.r;
+      lds[(pnl * 16 + cc) * GRAM_LD + ii] = ok ? (double)x[it] : 0.0;
     }
     __syncthreads();
     const int nq = (int)((min((int64_t)GRAM_ROWS, a.n - i0) + 3) / 4);

@@ -49,7 +49,8 @@ PEAK_HBM_GBS = 8000.0
 # known size.  They hold for the kernel sources whose hash is stored with them
 # and are reported as null once those sources change.
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
-                   "paper_1911_03813_amd/csrc/kcommon.hpp")
+                   "paper_1911_03813_amd/csrc/kcommon.hpp", "paper_1911_03813_amd/csrc/lp_kernels.hip",
+                   "paper_1911_03813_amd/csrc/lp.hpp")
 TRAFFIC_SHA = "75e213583d827026"
 TRAFFIC_BYTES = {("fp32", "gemm1"): 492.1e6, ("fp32", "gemm2"): 474.4e6,
                  ("fp64", "gemm1"): 1796.3e6, ("fp64", "gemm2"): 1748.7e6}
@@ -392,8 +393,22 @@ def main():
     # divided by its summed launch time per step
     dom = max(("gemm1", "gemm2"), key=lambda k: per_kernel.get(k, {"step_us": 0})["step_us"])
     dom_us = per_kernel[dom]["step_us"]
-    achieved = mult * flop_gemm / (dom_us * 1e-6) / 1e12
     traffic = traffic_for(args.prec, dom)
+    if lowp:
+        # the 16-bit products stream V at ~112 flop per byte (2 r flop per
+        # 2-byte value), under the ridge 2500 / 8 = 312: HBM-bound.  Their
+        # algorithmic bytes: V's 16-bit copy (both planes for bf16x3), A's
+        # copy and W (written by gemm1, read by gemm2), all once.
+        planes = 2 if args.prec == "bf16x3" else 1
+        alg_bytes = 2.0 * planes * (n * p + n * r + p * r)
+        roof = {"kernel": dom, "bound": "hbm", "achieved": alg_bytes / (dom_us * 1e-6) / 1e9, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "algorithmic_bytes": alg_bytes}
+    else:
+        roof = {"kernel": dom, "bound": "mfma", "achieved": mult * flop_gemm / (dom_us * 1e-6) / 1e12, "peak": peak,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof["launches_per_step"] = per_kernel[dom]["launches"] / args.steps
 
     res = {
         "metric": "f+grad f evals/s (n=1000, p=1e5, r=100, d=3)",
@@ -411,9 +426,7 @@ def main():
         "config": {"workload": "large single instance: Gaussian mixture d=3 n=1000 r=100 p=100000 sigma=1e-2",
                    "d": d, "n": n, "r": r, "p": p, "precision": args.prec, "storage": args.prec},
         "step_mfma_frac": mult * flop_step * evals / (peak * 1e12),
-        "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "launches_per_step": per_kernel[dom]["launches"] / args.steps},
+        "roofline": roof,
         "kernels_us_per_step": {k: round(v["step_us"], 2) for k, v in breakdown.items()},
         "kernels_us_per_step_note": f"every kernel, timed over {bsteps} steps after the timed region",
     }

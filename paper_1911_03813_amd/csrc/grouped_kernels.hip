@@ -78,11 +78,12 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
         for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::mac(v.e[s], a[t].e[s], acc[t]);
     }
     // epilogue: acc[t][v] = z at l = 16 b + row(g, v), column col0 + 16 t + c
-    double nl[4];
+    double nl[4];   // clamped loads without branches, issued together
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t lv = 16 * b + Mfma<T>::row(g, v);
-      nl[v] = lv < p ? I.nu[lv] : 0.0;
+      const double x = I.nu[lv < p ? lv : p - 1];
+      nl[v] = lv < p ? x : 0.0;
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {

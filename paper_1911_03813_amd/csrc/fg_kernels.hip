@@ -39,7 +39,7 @@ namespace symtd {
 // observation columns and the factor columns into LDS, each column as one
 // contiguous run of G1_RUN bytes (QPC quads of 4 elements), and the waves read
 // their MFMA fragments from LDS.  LDS holds a column's quads at a swizzled
-// slot (quad q of column col at col*QPC + (q ^ ((col/2) mod QPC))), so the 16
+// slot (quad q of column col at col*QPC + (q ^ (col mod QPC))), so the 16
 // columns of one fragment read fall in distinct banks.
 //
 // When the observations are 16-byte aligned with n a multiple of 4, the
@@ -125,8 +125,8 @@ __global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) wsum[t] = 0.0;
 
-  auto swz = [](int col, int q) { return col * QPC + (q ^ ((col >> 1) & (QPC - 1))); };
-  auto unswz = [](int P, int& col, int& q) { col = P / QPC; q = (P % QPC) ^ ((col >> 1) & (QPC - 1)); };
+  auto swz = [](int col, int q) { return col * QPC + (q ^ (col & (QPC - 1))); };
+  auto unswz = [](int P, int& col, int& q) { col = P / QPC; q = (P % QPC) ^ (col & (QPC - 1)); };
   auto vcolumn = [&](int64_t sl, int col) {
     int64_t l = (int64_t)VCOLS * sl + col;
     return a.V + (l < a.p ? l : (int64_t)a.p - 1) * a.ldv;    // columns past p: weight 0

@@ -75,10 +75,15 @@ struct LpStage {
   static constexpr int XP = (XU + 255) / 256;                   // pieces per thread
   static constexpr int YP = (YU + 255) / 256;
   static constexpr int DPC = XP + YP;
-  static __device__ __forceinline__ int swz(int col, int q) { return col * U + (q ^ ((col >> 1) & (U - 1))); }
+  // 16-byte unit q of column col at col U + (q ^ ((col / R) mod U)), R = 16 / U
+  // columns per 256-byte bank row: the 16 columns of a fragment read land in
+  // 16 distinct 16-byte slots of the bank rows
+  static constexpr int RSH = U >= 16 ? 0 : U == 8 ? 1 : 2;
+  static_assert(U == 4 || U == 8 || U >= 16, "units per column");
+  static __device__ __forceinline__ int swz(int col, int q) { return col * U + (q ^ ((col >> RSH) & (U - 1))); }
   static __device__ __forceinline__ void unswz(int s, int& col, int& q) {
     col = s / U;
-    q = (s % U) ^ ((col >> 1) & (U - 1));
+    q = (s % U) ^ ((col >> RSH) & (U - 1));
   }
 };
 

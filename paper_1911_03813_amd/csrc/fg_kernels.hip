@@ -238,12 +238,27 @@ __global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
     __syncthreads();
   };
 
+  // weights of the slab being multiplied, for its owner's epilogue: loaded
+  // (clamped, without branches) when the slab begins and kept as loaded, so
+  // that they arrive with the slab's first chunk
+  double nlr[MT][4];
+  auto load_nu = [&](int64_t sl) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t l = 16 * ((int64_t)NW * MT * sl + MT * wave + m) + Mfma<T>::row(g, v);
+        nlr[m][v] = a.nu[l < a.p ? l : (int64_t)a.p - 1];
+      }
+  };
+
   if (u0 < u1) {
     int64_t sl = u0 / KC, kb = u0 - sl * KC;
     const int64_t sl_last = (u1 - 1) / KC;
     while (true) {
       const int64_t ke = (sl == sl_last) ? u1 - sl * KC : KC;
       const int64_t nk = ke - kb;
+      if (kb == 0) load_nu(sl);
       if constexpr (DMA) {
         if constexpr (NS == 3) {
           // chunk kb+q lives in stage q mod 3
@@ -329,26 +344,35 @@ __global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
           __syncthreads();   // every wave has read the partial before the flag is lowered
           if (tid == 0) __hip_atomic_store(a.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // epilogue: acc[m][t][v] = z at l = 16 b + row(g, v), j = col0 + 16t + c
+        // epilogue: acc[m][t][v] = z at l = 16 b + row(g, v), j = col0 + 16t + c.
+        // w = nu z^(d-1) in the storage precision, the power taken over all
+        // of the lane's values at once (the exponent loop outside, so that
+        // the products are independent); the sums of w z in fp64.  nlr holds
+        // the slab's weights, loaded when the slab began.
+        acc_t zp[MT][NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) zp[m][t] = acc_t{1, 1, 1, 1};
+        for (int e = 0; e < dm1; ++e)
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) zp[m][t] *= acc[m][t];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           const int64_t b = (int64_t)NW * MT * sl + MT * wave + m;   // 16-observation block
-          double nl[4];   // clamped loads without branches: issued together
+          T nl[4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t l = 16 * b + Mfma<T>::row(g, v);
-            const double x = a.nu[l < a.p ? l : (int64_t)a.p - 1];
-            nl[v] = (l < a.p) ? x : 0.0;
-          }
+          for (int v = 0; v < 4; ++v) nl[v] = 16 * b + Mfma<T>::row(g, v) < a.p ? (T)nlr[m][v] : T(0);
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             Quad<T> wq;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const double z = (double)acc[m][t][v];
-              const double wv = nl[v] * ipow(z, dm1);
-              wq.e[v] = (T)wv;
-              wsum[t] += wv * z;
+              const T wv = nl[v] * zp[m][t][v];
+              wq.e[v] = wv;
+              wsum[t] += (double)wv * (double)acc[m][t][v];
             }
             if (b < a.nblk) vstore4(a.Wp + (((b * a.nt_tot + tg + t) * 64) + lane) * 4, wq);
           }

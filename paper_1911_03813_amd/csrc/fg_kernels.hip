@@ -34,7 +34,7 @@ namespace symtd {
 // gemm1 + epilogue
 //
 // A block of G1_WAVES waves works in lockstep on one slab of
-// 16*G1_MT*G1_WAVES observations (16*G1_MT per wave).  The k range (the n covariates) is cut into
+// 16*MT*G1_WAVES observations (16*MT per wave, MT = g1_mt<T>()).  The k range (the n covariates) is cut into
 // chunks of KCH = 4*QPC; for every chunk the block moves the slab's
 // observation columns and the factor columns into LDS, each column as one
 // contiguous run of G1_RUN bytes (QPC quads of 4 elements), and the waves read
@@ -82,7 +82,7 @@ template <typename T, int NT, bool DMA>
 __global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int NW = G1_WAVES;
-  constexpr int MT = G1_MT;
+  constexpr int MT = g1_mt<T>();
   constexpr int NTH = 64 * NW;
   constexpr int NS = G1_STAGES;
   constexpr int QPC = G1Shape<T>::QPC;
@@ -758,6 +758,9 @@ void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<doub
     case 2: DF64::g1<2>(vec, grid, st, a); break;
     case 3: DF64::g1<3>(vec, grid, st, a); break;
     case 4: DF64::g1<4>(vec, grid, st, a); break;
+    case 5: DF64::g1<5>(vec, grid, st, a); break;
+    case 6: DF64::g1<6>(vec, grid, st, a); break;
+    case 7: DF64::g1<7>(vec, grid, st, a); break;
     default: break;
   }
 }
@@ -779,6 +782,9 @@ void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<doub
     case 2: DF64::g2<2>(vec, grid, st, a); break;
     case 3: DF64::g2<3>(vec, grid, st, a); break;
     case 4: DF64::g2<4>(vec, grid, st, a); break;
+    case 5: DF64::g2<5>(vec, grid, st, a); break;
+    case 6: DF64::g2<6>(vec, grid, st, a); break;
+    case 7: DF64::g2<7>(vec, grid, st, a); break;
     default: break;
   }
 }

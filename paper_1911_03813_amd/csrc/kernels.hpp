@@ -10,11 +10,11 @@ namespace symtd {
 
 // Column subtiles handled by one launch of gemm1/gemm2 (16 columns each);
 // wider ranks are processed in several column groups.
-// Both products handle up to 7 in one launch for fp32 and 4 for fp64.
+// Both products handle up to 7 in one launch (fp32 and fp64).
 constexpr int NT_MAX_G1_F32 = 7;
-constexpr int NT_MAX_G1_F64 = 4;
+constexpr int NT_MAX_G1_F64 = 7;
 constexpr int NT_MAX_G2_F32 = 7;
-constexpr int NT_MAX_G2_F64 = 4;
+constexpr int NT_MAX_G2_F64 = 7;
 // gemm1 shape: waves per block, M subtiles (16 observations) per wave, bytes
 // of one column run per chunk, and LDS stages of the chunk ring.
 #ifndef SYMTD_G1_WAVES
@@ -33,6 +33,10 @@ constexpr int G1_WAVES = SYMTD_G1_WAVES;
 constexpr int G1_MT = SYMTD_G1_MT;
 constexpr int G1_RUN = SYMTD_G1_RUN;
 constexpr int G1_STAGES = SYMTD_G1_STAGES;
+// M subtiles per wave of the first product: fp64 takes one, so that seven
+// column subtiles of fp64 accumulators fit the register file and r <= 112
+// needs one launch (V read once)
+template <typename T> constexpr int g1_mt() { return sizeof(T) == 8 ? 1 : G1_MT; }
 // Depth of the register prefetch ring of gemm2.
 constexpr int G2_STAGES_F32 = 3;
 constexpr int G2_STAGES_F64 = 2;
@@ -45,13 +49,13 @@ struct G1Args {
   int nt_tot;    // column subtiles over all groups: ceil(r / 16)
   int rp;        // 16 * nt_tot
   int nblk;      // ceil(p / 16) blocks of 16 observations (packed W)
-  int nslab;     // ceil(p / (16 * G1_MT * G1_WAVES)) block slabs
+  int nslab;     // ceil(p / (16 * g1_mt<T>() * G1_WAVES)) block slabs
   int nblocks;   // blocks taking part (<= nslab, all resident)
   int d;
   const T* Apad; int64_t ldap;   // zero-padded factor copy (see k_pack_a)
   T* Wp;         // packed W
   double* wpart; // [G1_WAVES * nblocks][rp] fp64 column partials, one row per wave
-  T* part;       // [nblocks][G1_WAVES * G1_MT * NT * 256] published partial accumulators
+  T* part;       // [nblocks][G1_WAVES * g1_mt<T>() * NT * 256] published partial accumulators
   int* flag;     // [nblocks] hand-off flags, zero between launches
   int* err;      // set to 1 if a hand-off wait gave up
 };

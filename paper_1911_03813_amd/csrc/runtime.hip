@@ -155,7 +155,8 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   P.nt1 = f64 ? NT_MAX_G1_F64 : NT_MAX_G1_F32;
   P.nt2 = f64 ? NT_MAX_G2_F64 : NT_MAX_G2_F32;
   // gemm1: one block per CU, never more blocks than slabs
-  P.nslab = (int)((p + 16 * G1_MT * G1_WAVES - 1) / (16 * G1_MT * G1_WAVES));
+  const int mt = f64 ? g1_mt<double>() : g1_mt<float>();
+  P.nslab = (int)((p + 16 * mt * G1_WAVES - 1) / (16 * mt * G1_WAVES));
   P.nblocks = (int)std::min<int64_t>(g1_blocks > 0 ? std::min<int64_t>(g1_blocks, cus) : cus, P.nslab);
   // gemm2: row blocks of 256 x splits of the observations, one block per CU
   P.npad = ((n + 255) / 256) * 256;
@@ -170,7 +171,7 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   P.apad = (size_t)P.rp * P.ldap;
   P.wp = (size_t)P.nblk * 16 * P.rp;
   P.wpart = (size_t)G1_WAVES * P.nblocks * P.rp;
-  P.part = (size_t)P.nblocks * G1_WAVES * G1_MT * P.nt1 * 256;
+  P.part = (size_t)P.nblocks * G1_WAVES * mt * P.nt1 * 256;
   P.ypart = (size_t)P.nsplit * P.rp * P.npad;
   P.rr = (size_t)r * r;
   P.fp = (size_t)r;

@@ -222,9 +222,43 @@ __global__ __launch_bounds__(64) void k_ggemm2(const GInst<T>* insts, const GIte
 
 // ---------------------------------------------------------------------------
 // gmodel: one block per (instance, model): B, C, u, w, f, g_lambda, Y_M (fp64)
+//
+// For r <= GM_RMAX the block moves the model's A to LDS in chunks of GM_ROWS
+// rows (every load of a chunk issued before any is used) and keeps B and C in
+// LDS; larger r reads A from global memory directly.  Both ways take every
+// sum in the same order (B over i ascending, Y_M over l ascending), so the
+// results are the same bits.
 // ---------------------------------------------------------------------------
+constexpr int GM_RMAX = 32;
+constexpr int GM_ROWS = 64;
+
+// the chunk of rows [i0, i0 + GM_ROWS) of A (r <= GM_RMAX columns) into
+// sA[ii][l] as fp64 (times lambda_l when lam is given), zero past n
+template <typename T>
+__device__ __forceinline__ void gm_stage(const T* A, int64_t lda, int n, int r, int64_t i0, const double* lam,
+                                         double (*sA)[GM_RMAX + 1]) {
+  constexpr int IT = GM_ROWS * GM_RMAX / 256;
+  T x[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + 256 * it;
+    const int ii = e % GM_ROWS, l = min(e / GM_ROWS, r - 1);
+    const int64_t i = i0 + ii;
+    x[it] = A[(int64_t)l * lda + (i < n ? i : 0)];
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + 256 * it;
+    const int ii = e % GM_ROWS, l = e / GM_ROWS;
+    if (l < r) sA[ii][l] = i0 + ii < n ? (lam ? (double)x[it] * lam[l] : (double)x[it]) : 0.0;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GItem* items) {
+  __shared__ double sA[GM_ROWS][GM_RMAX + 1];
+  __shared__ double sB[GM_RMAX * GM_RMAX], sC[GM_RMAX * GM_RMAX];
+  __shared__ double fs[256];
   const GItem it = items[blockIdx.x];
   const GInst<T> I = insts[it.inst];
   const int k = it.a;                       // model
@@ -234,29 +268,73 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
   const double* lam = I.lam + (int64_t)k * r;
   double* B = I.B + k * rr;
   double* C = I.C + k * rr;
+  const bool fast = r <= GM_RMAX;
   // B = A'A (upper pairs, mirrored), C = B^{d-1}
-  for (int e = threadIdx.x; e < r * r; e += 256) {
-    const int j = e % r, l = e / r;
-    if (j > l) continue;
-    const T* aj = A + (int64_t)j * I.lda;
-    const T* al = A + (int64_t)l * I.lda;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s = fma((double)aj[i], (double)al[i], s);
-    const double cv = ipow(s, I.d - 1);
-    B[(int64_t)l * r + j] = s; B[(int64_t)j * r + l] = s;
-    C[(int64_t)l * r + j] = cv; C[(int64_t)j * r + l] = cv;
+  if (fast) {
+    // thread t takes the pairs e = t, t + 256, ... (j <= l), at most
+    // GM_RMAX^2 / 256 of them
+    constexpr int PP = GM_RMAX * GM_RMAX / 256;
+    double s[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) s[q] = 0.0;
+    for (int64_t i0 = 0; i0 < n; i0 += GM_ROWS) {
+      gm_stage(A, I.lda, n, r, i0, nullptr, sA);
+      __syncthreads();
+      const int rows = (int)min((int64_t)GM_ROWS, n - i0);
+#pragma unroll
+      for (int q = 0; q < PP; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int j = e % GM_RMAX, l = e / GM_RMAX;
+        if (j < r && l < r && j <= l)
+          for (int ii = 0; ii < rows; ++ii) s[q] = fma(sA[ii][j], sA[ii][l], s[q]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int j = e % GM_RMAX, l = e / GM_RMAX;
+      if (j < r && l < r && j <= l) {
+        const double cv = ipow(s[q], I.d - 1);
+        B[(int64_t)l * r + j] = s[q]; B[(int64_t)j * r + l] = s[q];
+        C[(int64_t)l * r + j] = cv; C[(int64_t)j * r + l] = cv;
+        sB[l * r + j] = s[q]; sB[j * r + l] = s[q];
+        sC[l * r + j] = cv; sC[j * r + l] = cv;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < r * r; e += 256) {
+      const int j = e % r, l = e / r;
+      if (j > l) continue;
+      const T* aj = A + (int64_t)j * I.lda;
+      const T* al = A + (int64_t)l * I.lda;
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s = fma((double)aj[i], (double)al[i], s);
+      const double cv = ipow(s, I.d - 1);
+      B[(int64_t)l * r + j] = s; B[(int64_t)j * r + l] = s;
+      C[(int64_t)l * r + j] = cv; C[(int64_t)j * r + l] = cv;
+    }
   }
   __syncthreads();
+  const double* Bs = fast ? sB : B;
+  const double* Cs = fast ? sC : C;
   // u, w, g_lambda and f: thread t handles columns t, t + 256, ... and its
   // share of f; the shares are then summed in thread order
-  __shared__ double fs[256];
   double fsh = 0.0;
   for (int j = threadIdx.x; j < r; j += 256) {
     double u = 0.0;
-    for (int l = 0; l < r; ++l) u += B[(int64_t)l * r + j] * C[(int64_t)l * r + j] * lam[l];
-    double w = 0.0;
+    for (int l = 0; l < r; ++l) u += Bs[(int64_t)l * r + j] * Cs[(int64_t)l * r + j] * lam[l];
     const int col = k * r + j;
-    for (int t = 0; t < I.ntile; ++t) w += I.wpart[(int64_t)t * I.cols + col];
+    // the tile partials of w, loaded eight at a time from valid rows
+    double w = 0.0;
+    for (int t0 = 0; t0 < I.ntile; t0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int h = 0; h < 8; ++h) v[h] = I.wpart[(int64_t)min(t0 + h, I.ntile - 1) * I.cols + col];
+#pragma unroll
+      for (int h = 0; h < 8; ++h)
+        if (t0 + h < I.ntile) w += v[h];
+    }
     I.glam[col] = -2.0 * (w - u);
     fsh += lam[j] * u - 2.0 * w * lam[j];
   }
@@ -268,11 +346,26 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
     I.f[k] = I.alpha + f;
   }
   // Y_M = A D_lambda C for this model's columns
-  for (int e = threadIdx.x; e < n * r; e += 256) {
-    const int i = e % n, j = e / n;
-    double s = 0.0;
-    for (int l = 0; l < r; ++l) s = fma((double)A[(int64_t)l * I.lda + i] * lam[l], C[(int64_t)j * r + l], s);
-    I.YM[((int64_t)k * r + j) * n + i] = s;
+  if (fast) {
+    for (int64_t i0 = 0; i0 < n; i0 += GM_ROWS) {
+      __syncthreads();                       // the previous chunk (or B's) is read
+      gm_stage(A, I.lda, n, r, i0, lam, sA);
+      __syncthreads();
+      const int rows = (int)min((int64_t)GM_ROWS, n - i0);
+      for (int e = threadIdx.x; e < rows * r; e += 256) {
+        const int ii = e % rows, j = e / rows;
+        double s = 0.0;
+        for (int l = 0; l < r; ++l) s = fma(sA[ii][l], sC[j * r + l], s);
+        I.YM[((int64_t)k * r + j) * n + i0 + ii] = s;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < n * r; e += 256) {
+      const int i = e % n, j = e / n;
+      double s = 0.0;
+      for (int l = 0; l < r; ++l) s = fma((double)A[(int64_t)l * I.lda + i] * lam[l], C[(int64_t)j * r + l], s);
+      I.YM[((int64_t)k * r + j) * n + i] = s;
+    }
   }
 }
 
@@ -287,8 +380,16 @@ __global__ __launch_bounds__(256) void k_gfinal(const GInst<T>* insts, const GIt
   const int64_t rp = (int64_t)I.nt * 16;
   const double lj = I.lam[col];
   for (int i = threadIdx.x; i < I.n; i += 256) {
+    // the split partials, loaded eight at a time from valid splits, summed in order
     double y = 0.0;
-    for (int sp = 0; sp < I.nsplit; ++sp) y += (double)I.Ypart[((int64_t)sp * rp + col) * I.ldy + i];
+    for (int s0 = 0; s0 < I.nsplit; s0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int h = 0; h < 8; ++h) v[h] = I.Ypart[((int64_t)min(s0 + h, I.nsplit - 1) * rp + col) * I.ldy + i];
+#pragma unroll
+      for (int h = 0; h < 8; ++h)
+        if (s0 + h < I.nsplit) y += (double)v[h];
+    }
     const double gval = -2.0 * I.d * (y - I.YM[(int64_t)col * I.n + i]) * lj;
     I.G[(int64_t)col * I.ldg + i] = (T)gval;
   }

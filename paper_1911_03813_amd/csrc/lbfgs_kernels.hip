@@ -37,10 +37,14 @@ constexpr double LB_COLLAPSE = 1e-14;
 enum { EX_PGTOL = 1, EX_FTOL = 2, EX_MAX_ITERS = 3, EX_MAX_EVALS = 4, EX_LINESEARCH = 5, EX_NONFINITE = 6 };
 
 // trial gradient element e of a lane (divided by the scale)
+// (both sources are read from valid elements and the value selected after:
+// a conditional load would be a branch that waits for its value)
 template <typename T>
 __device__ __forceinline__ double trial_grad(const LbLane<T>& ln, int64_t e) {
-  const double raw = e < ln.r ? ln.glam_t[e] : (double)ln.G_t[e - ln.r];
-  return raw / ln.scale;
+  const bool lam = e < ln.r;
+  const double a = ln.glam_t[lam ? e : ln.r - 1];
+  const double b = (double)ln.G_t[lam ? 0 : e - ln.r];
+  return (lam ? a : b) / ln.scale;
 }
 
 template <typename T>
@@ -93,14 +97,22 @@ __global__ __launch_bounds__(256) void k_lb_dots(const LbLane<T>* lanes) {
     acc[LB_YTD] = fma(yt, de, acc[LB_YTD]);
     acc[LB_YTGT] = fma(yt, gt, acc[LB_YTGT]);
     mx = fmax(mx, fabs(gt));
+    // the stored pairs: every slot read (unused ones from slot 0, a valid
+    // one), so that all loads are in flight together; only s < cnt count
+    double Sv[LB_MMAX], Yv[LB_MMAX];
+#pragma unroll
+    for (int s = 0; s < LB_MMAX; ++s) {
+      const int64_t sq = s < cnt ? s : 0;
+      Sv[s] = ln.S[sq * ln.N + e];
+      Yv[s] = ln.Y[sq * ln.N + e];
+    }
 #pragma unroll
     for (int s = 0; s < LB_MMAX; ++s) {
       if (s < cnt) {
-        const double Ss = ln.S[(int64_t)s * ln.N + e], Ys = ln.Y[(int64_t)s * ln.N + e];
-        acc[LB_GTS + s] = fma(gt, Ss, acc[LB_GTS + s]);
-        acc[LB_GTY + s] = fma(gt, Ys, acc[LB_GTY + s]);
-        acc[LB_SYT + s] = fma(Ss, yt, acc[LB_SYT + s]);
-        acc[LB_YYT + s] = fma(Ys, yt, acc[LB_YYT + s]);
+        acc[LB_GTS + s] = fma(gt, Sv[s], acc[LB_GTS + s]);
+        acc[LB_GTY + s] = fma(gt, Yv[s], acc[LB_GTY + s]);
+        acc[LB_SYT + s] = fma(Sv[s], yt, acc[LB_SYT + s]);
+        acc[LB_YYT + s] = fma(Yv[s], yt, acc[LB_YYT + s]);
       }
     }
   }
@@ -429,13 +441,21 @@ __global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes) {
           ln.S[(int64_t)slot * ln.N + e] = snew;
           ln.Y[(int64_t)slot * ln.N + e] = ynew;
         }
+        // every slot read (unused ones from a valid slot) before any is used
+        double Sv[LB_MMAX], Yv[LB_MMAX];
+#pragma unroll
+        for (int q = 0; q < LB_MMAX; ++q) {
+          const int64_t sq = q < cnt ? q : 0;
+          Sv[q] = ln.S[sq * ln.N + e];
+          Yv[q] = ln.Y[sq * ln.N + e];
+        }
         double dn = coef_g * gt;
 #pragma unroll
         for (int q = 0; q < LB_MMAX; ++q) {
           if (q < cnt) {
             const bool fresh = store && q == slot;
-            const double Sq = fresh ? snew : ln.S[(int64_t)q * ln.N + e];
-            const double Yq = fresh ? ynew : ln.Y[(int64_t)q * ln.N + e];
+            const double Sq = fresh ? snew : Sv[q];
+            const double Yq = fresh ? ynew : Yv[q];
             dn = fma(cs[q], Sq, fma(cy[q], Yq, dn));
           }
         }

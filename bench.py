@@ -51,11 +51,11 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
                    "paper_1911_03813_amd/csrc/kcommon.hpp", "paper_1911_03813_amd/csrc/lp_kernels.hip",
                    "paper_1911_03813_amd/csrc/lp.hpp")
-TRAFFIC_SHA = "beb5978b21a1ceba"
-TRAFFIC_BYTES = {("fp32", "gemm1"): 511.3e6, ("fp32", "gemm2"): 474.3e6,
-                 ("fp64", "gemm1"): 1876.5e6, ("fp64", "gemm2"): 1749.0e6,
+TRAFFIC_SHA = "7c97641400834dbb"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 506.7e6, ("fp32", "gemm2"): 474.3e6,
+                 ("fp64", "gemm1"): 977.9e6, ("fp64", "gemm2"): 948.5e6,
                  ("fp16", "gemm1"): 269.6e6, ("fp16", "gemm2"): 237.5e6,
-                 ("bf16x3", "gemm1"): 501.8e6, ("bf16x3", "gemm2"): 460.1e6}
+                 ("bf16x3", "gemm1"): 501.7e6, ("bf16x3", "gemm2"): 460.1e6}
 
 
 def traffic_for(prec, kernel):

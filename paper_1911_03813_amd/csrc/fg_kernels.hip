@@ -33,8 +33,8 @@ namespace symtd {
 // ---------------------------------------------------------------------------
 // gemm1 + epilogue
 //
-// A block of G1_WAVES waves works in lockstep on one slab of
-// 16*MT*G1_WAVES observations (16*MT per wave, MT = g1_mt<T>()).  The k range (the n covariates) is cut into
+// A block of NW = g1_waves<T>() waves works in lockstep on one slab of
+// 16*MT*NW observations (16*MT per wave, MT = g1_mt<T>()).  The k range (the n covariates) is cut into
 // chunks of KCH = 4*QPC; for every chunk the block moves the slab's
 // observation columns and the factor columns into LDS, each column as one
 // contiguous run of G1_RUN bytes (QPC quads of 4 elements), and the waves read
@@ -79,9 +79,9 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 template <typename T, int NT, bool DMA>
-__global__ __launch_bounds__(64 * G1_WAVES) void k_gemm1(G1Args<T> a) {
+__global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   using acc_t = typename Mfma<T>::acc_t;
-  constexpr int NW = G1_WAVES;
+  constexpr int NW = g1_waves<T>();
   constexpr int MT = g1_mt<T>();
   constexpr int NTH = 64 * NW;
   constexpr int NS = G1_STAGES;
@@ -727,8 +727,8 @@ template <typename T, int NS2>
 struct Dispatch {
   template <int NTV>
   static void g1(bool dma, dim3 grid, hipStream_t st, const G1Args<T>& a) {
-    if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true>), grid, dim3(64 * G1_WAVES), 0, st, a);
-    else hipLaunchKernelGGL((k_gemm1<T, NTV, false>), grid, dim3(64 * G1_WAVES), 0, st, a);
+    if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm1<T, NTV, false>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
   }
   template <int NTV>
   static void g2(bool vec, dim3 grid, hipStream_t st, const G2Args<T>& a) {

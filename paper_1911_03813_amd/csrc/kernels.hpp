@@ -37,6 +37,10 @@ constexpr int G1_STAGES = SYMTD_G1_STAGES;
 // column subtiles of fp64 accumulators fit the register file and r <= 112
 // needs one launch (V read once)
 template <typename T> constexpr int g1_mt() { return sizeof(T) == 8 ? 1 : G1_MT; }
+// Waves per block of the first product: fp64 takes eight one-subtile waves
+// (two per SIMD, so that one multiplies while the other waits at a stage
+// boundary; its registers allow it), fp32 G1_WAVES two-subtile waves.
+template <typename T> constexpr int g1_waves() { return sizeof(T) == 8 ? 8 : G1_WAVES; }
 // Depth of the register prefetch ring of gemm2.
 constexpr int G2_STAGES_F32 = 3;
 constexpr int G2_STAGES_F64 = 2;
@@ -49,13 +53,13 @@ struct G1Args {
   int nt_tot;    // column subtiles over all groups: ceil(r / 16)
   int rp;        // 16 * nt_tot
   int nblk;      // ceil(p / 16) blocks of 16 observations (packed W)
-  int nslab;     // ceil(p / (16 * g1_mt<T>() * G1_WAVES)) block slabs
+  int nslab;     // ceil(p / (16 * g1_mt<T>() * g1_waves<T>())) block slabs
   int nblocks;   // blocks taking part (<= nslab, all resident)
   int d;
   const T* Apad; int64_t ldap;   // zero-padded factor copy (see k_pack_a)
   T* Wp;         // packed W
-  double* wpart; // [G1_WAVES * nblocks][rp] fp64 column partials, one row per wave
-  T* part;       // [nblocks][G1_WAVES * g1_mt<T>() * NT * 256] published partial accumulators
+  double* wpart; // [g1_waves<T>() * nblocks][rp] fp64 column partials, one row per wave
+  T* part;       // [nblocks][g1_waves<T>() * g1_mt<T>() * NT * 256] published partial accumulators
   int* flag;     // [nblocks] hand-off flags, zero between launches
   int* err;      // set to 1 if a hand-off wait gave up
 };

@@ -128,7 +128,7 @@ template <typename X>
 bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct FgPlan {
-  int nt_tot, rp, nblk, nt1, nt2, nslab, nblocks, nsplit, blk_per_split, rowblocks;
+  int nt_tot, rp, nblk, nt1, nt2, g1w, nslab, nblocks, nsplit, blk_per_split, rowblocks;
   int64_t npad;
   int64_t ldap;
   size_t apad, wp, wpart, part, ypart, rr, fp;  // element counts
@@ -156,7 +156,8 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   P.nt2 = f64 ? NT_MAX_G2_F64 : NT_MAX_G2_F32;
   // gemm1: one block per CU, never more blocks than slabs
   const int mt = f64 ? g1_mt<double>() : g1_mt<float>();
-  P.nslab = (int)((p + 16 * mt * G1_WAVES - 1) / (16 * mt * G1_WAVES));
+  P.g1w = f64 ? g1_waves<double>() : g1_waves<float>();
+  P.nslab = (int)((p + 16 * mt * P.g1w - 1) / (16 * mt * P.g1w));
   P.nblocks = (int)std::min<int64_t>(g1_blocks > 0 ? std::min<int64_t>(g1_blocks, cus) : cus, P.nslab);
   // gemm2: row blocks of 256 x splits of the observations, one block per CU
   P.npad = ((n + 255) / 256) * 256;
@@ -170,8 +171,8 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   P.ldap = ((n + kch - 1) / kch) * kch;
   P.apad = (size_t)P.rp * P.ldap;
   P.wp = (size_t)P.nblk * 16 * P.rp;
-  P.wpart = (size_t)G1_WAVES * P.nblocks * P.rp;
-  P.part = (size_t)P.nblocks * G1_WAVES * mt * P.nt1 * 256;
+  P.wpart = (size_t)P.g1w * P.nblocks * P.rp;
+  P.part = (size_t)P.nblocks * P.g1w * mt * P.nt1 * 256;
   P.ypart = (size_t)P.nsplit * P.rp * P.npad;
   P.rr = (size_t)r * r;
   P.fp = (size_t)r;
@@ -248,7 +249,7 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
     const int ct = (int)((r1 + FINAL_COLS - 1) / FINAL_COLS);
     const int64_t ntile = ((n + 63) / 64) * ct * ng;
     FinalArgs<T> fa{Ypart, P.npad, P.rp, P.nsplit, 1.0, A, lda, (int)n, (int)r1, ng, ct, lambda, B, C, d,
-                    wpart, (int64_t)G1_WAVES * P.nblocks, alpha, G, ldg, fpart, f, g_lambda, ctx->final_count,
+                    wpart, (int64_t)P.g1w * P.nblocks, alpha, G, ldg, fpart, f, g_lambda, ctx->final_count,
                     ntile};
     launch_final(st, fa);
   }

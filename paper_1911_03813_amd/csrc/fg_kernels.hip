@@ -314,7 +314,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 
       if (kb > 0) {
         // not the owner: publish this block's partial for the previous block
-        T* pp = a.part + blk * PART + (int64_t)wave * (MT * NT * 4 * 64);
+        T* pp = a.part + opaque_uniform(blk) * PART + (int64_t)wave * (MT * NT * 4 * 64);
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
         if (ke < KC) {
           // the next block holds chunks [ke, KC) of this slab
           xwait_flag(a.flag + blk + 1, a.err);
-          const T* pp = a.part + (blk + 1) * PART + (int64_t)wave * (MT * NT * 4 * 64);
+          const T* pp = a.part + opaque_uniform(blk + 1) * PART + (int64_t)wave * (MT * NT * 4 * 64);
 #pragma unroll
           for (int m = 0; m < MT; ++m)
 #pragma unroll

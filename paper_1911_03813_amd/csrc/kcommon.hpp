@@ -155,6 +155,15 @@ __device__ __forceinline__ v4f xget4v(const float* p) {
 // every store this thread issued is complete (s_waitcnt with all counts 0)
 __device__ __forceinline__ void xput_complete() { __builtin_amdgcn_s_waitcnt(0); }
 
+// The same wave-uniform value, hidden from loop-invariant code motion.  An
+// address used only where a slab ends (a stream-K partial, say) is otherwise
+// computed once before the slab loop and kept alive, or spilled, across the
+// whole chunk loop; built from this value it is computed where it is used.
+__device__ __forceinline__ int64_t opaque_uniform(int64_t x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 // Spin until a hand-off flag is raised (relaxed device-scope loads), giving
 // up after a bounded number of polls: then *err is set and the caller goes
 // on with whatever the partial holds, so that every wave still exits.

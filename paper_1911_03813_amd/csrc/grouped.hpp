@@ -23,8 +23,9 @@ namespace symtd {
 
 constexpr int GG1_TILE = 256;        // observations per ggemm1 item (4 waves x 4 blocks of 16)
 constexpr int GG2_SPLIT_BLK = 16;    // 16-observation blocks per ggemm2 split (256 observations)
-constexpr int GG_NT_F32 = 8;         // column subtiles per item (fp32)
+constexpr int GG_NT_F32 = 4;         // column subtiles per item (fp32): few enough registers for three waves per SIMD
 constexpr int GG_NT_F64 = 4;         // column subtiles per item (fp64)
+constexpr int GG_NT_MAX = GG_NT_F32 > GG_NT_F64 ? GG_NT_F32 : GG_NT_F64;
 
 template <typename T>
 struct GInst {

@@ -29,7 +29,7 @@ __device__ __forceinline__ void quad_at(Quad<T>& q, const T* col, int64_t i, int
 // ggemm1 body for NT column subtiles
 // ---------------------------------------------------------------------------
 template <typename T, int NT, bool VEC>
-__device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[GG_NT_F32 * 16]) {
+__device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[GG_NT_MAX * 16]) {
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int NTM = std::is_same<T, float>::value ? GG_NT_F32 : GG_NT_F64;
   const int lane = threadIdx.x & 63;
@@ -173,7 +173,7 @@ __device__ void ggemm2_body(const GInst<T>& I, int rb, int split, int cg) {
 
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_ggemm1(const GInst<T>* insts, const GItem* items) {
-  __shared__ double red[4][GG_NT_F32 * 16];
+  __shared__ double red[4][GG_NT_MAX * 16];
   const GItem it = items[blockIdx.x];
   const GInst<T> I = insts[it.inst];
   constexpr int NTM = std::is_same<T, float>::value ? GG_NT_F32 : GG_NT_F64;

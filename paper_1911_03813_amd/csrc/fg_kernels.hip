@@ -471,6 +471,13 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
       for (int s = 0; s < NS; ++s) {
         issue((s + NS - 1) % NS, b0 + min(qb + s + NS - 1, Q - 1));
         compute(s);
+        if constexpr (sizeof(T) == 4 && VEC) {
+          // keep each step's loads ahead of its multiplies: left alone, the
+          // scheduler sinks the last step's loads to the end of the loop,
+          // which halves the distance they have to arrive
+          __builtin_amdgcn_sched_group_barrier(0x020, NT + 4, 0);   // vector-memory reads
+          __builtin_amdgcn_sched_group_barrier(0x008, 16 * NT, 0);  // MFMAs
+        }
       }
     }
 #pragma unroll

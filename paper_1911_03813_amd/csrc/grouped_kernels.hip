@@ -19,10 +19,20 @@ namespace symtd {
 
 namespace {
 
+// elements i .. i+3 of a column of n (zero past n).  VEC (leading dimension a
+// multiple of 4, 16-byte aligned columns): one 16-byte load of the quad,
+// clamped into the column's first 4 ceil(n/4) elements, then the elements
+// past n replaced by zero; no branch, so the load never waits on a test.
 template <typename T, bool VEC>
 __device__ __forceinline__ void quad_at(Quad<T>& q, const T* col, int64_t i, int64_t n) {
-  if (VEC && i + 3 < n) vload4(q, col + i);
-  else load_tail(q, col, i, n);
+  if constexpr (VEC) {
+    const int64_t n4 = (n + 3) & ~(int64_t)3;
+    vload4(q, col + (i < n4 ? i : n4 - 4));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q.e[e] = i + e < n ? q.e[e] : T(0);
+  } else {
+    load_tail(q, col, i, n);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -61,7 +71,6 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
     for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
     // the trip count is the same for every lane (MFMA is a whole-wave
     // operation); covariates at or past n read as zero
-#pragma unroll 2
     for (int64_t k0 = 0; k0 < n; k0 += 16) {
       const int64_t k = k0 + 4 * g;
       Quad<T> v;
@@ -126,6 +135,7 @@ __device__ void ggemm2_body(const GInst<T>& I, int rb, int split, int cg) {
   const int64_t n = I.n, p = I.p;
   const int64_t ibase = (int64_t)rb * 64;
   const int64_t il = ibase + 4 * c;
+  const int64_t n4 = (n + 3) & ~(int64_t)3;
   const int64_t nblk = (p + 15) / 16;
   const int64_t b0 = (int64_t)split * GG2_SPLIT_BLK;
   const int64_t b1 = min(nblk, b0 + GG2_SPLIT_BLK);
@@ -144,7 +154,9 @@ __device__ void ggemm2_body(const GInst<T>& I, int rb, int split, int cg) {
       int64_t l = 16 * b + Mfma<T>::row(g, s);
       l = l < p ? l : p - 1;            // rows of W past p are zero
       const T* col = I.V + l * I.ldv;
-      if (VEC && il + 3 < n) vload4(v[s], col + il);
+      // rows past n only reach rows of Y that are never read: VEC loads the
+      // quad clamped into the column without masking it
+      if constexpr (VEC) vload4(v[s], col + (il < n4 ? il : n4 - 4));
       else load_tail(v[s], col, il, n);
     }
 #pragma unroll

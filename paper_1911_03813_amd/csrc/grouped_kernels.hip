@@ -86,23 +86,30 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::mac(v.e[s], a[t].e[s], acc[t]);
     }
-    // epilogue: acc[t][v] = z at l = 16 b + row(g, v), column col0 + 16 t + c
-    double nl[4];   // clamped loads without branches, issued together
+    // epilogue: acc[t][v] = z at l = 16 b + row(g, v), column col0 + 16 t + c.
+    // w = nu z^(d-1) in the storage precision (the exponent loop outside, so
+    // that the products are independent), the sums of w z in fp64
+    T nl[4];   // clamped loads without branches, issued together
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t lv = 16 * b + Mfma<T>::row(g, v);
       const double x = I.nu[lv < p ? lv : p - 1];
-      nl[v] = lv < p ? x : 0.0;
+      nl[v] = lv < p ? (T)x : T(0);
     }
+    acc_t zp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) zp[t] = acc_t{1, 1, 1, 1};
+    for (int e = 0; e < dm1; ++e)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) zp[t] *= acc[t];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       Quad<T> wq;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double z = (double)acc[t][v];
-        const double wv = nl[v] * ipow(z, dm1);
-        wq.e[v] = (T)wv;
-        wsum[t] += wv * z;
+        const T wv = nl[v] * zp[t][v];
+        wq.e[v] = wv;
+        wsum[t] += (double)wv * (double)acc[t][v];
       }
       vstore4(I.Wp + ((b * I.nt + cg * NTM + t) * 64 + lane) * 4, wq);
     }

@@ -61,34 +61,47 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
 #pragma unroll
   for (int t = 0; t < NT; ++t) wsum[t] = 0.0;
   const int64_t nblk = (p + 15) / 16;
-  for (int q = 0; q < GG1_TILE / 64; ++q) {
+  // the wave's four 16-observation blocks b_q = 16 tile + 4 q + wave are
+  // multiplied together, so that each factor quad serves all four; blocks
+  // past the last are computed from a valid column and not written
+  constexpr int QB = GG1_TILE / 64;
+  const T* vcol[QB];
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int64_t l = 16 * ((int64_t)tile * (GG1_TILE / 16) + 4 * q + wave) + c;
+    vcol[q] = I.V + (l < p ? l : p - 1) * I.ldv;
+  }
+  acc_t acc[QB][NT];
+#pragma unroll
+  for (int q = 0; q < QB; ++q)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[q][t] = acc_t{0, 0, 0, 0};
+  for (int64_t k0 = 0; k0 < n; k0 += 16) {
+    const int64_t k = k0 + 4 * g;
+    Quad<T> v[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) quad_at<T, VEC>(v[q], vcol[q], k, n);
+    Quad<T> a[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      quad_at<T, VEC>(a[t], acol[t], k, n);
+      if (!aok[t]) zero4(a[t]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[q][t] = Mfma<T>::mac(v[q].e[s], a[t].e[s], acc[q][t]);
+  }
+  // epilogue per block: acc[q][t][v] = z at l = 16 b + row(g, v), column
+  // col0 + 16 t + c.  w = nu z^(d-1) in the storage precision (the exponent
+  // loop outside, so that the products are independent), the sums of w z in
+  // fp64, block by block
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
     const int64_t b = (int64_t)tile * (GG1_TILE / 16) + 4 * q + wave;
     if (b >= nblk) break;
-    const int64_t l = 16 * b + c;
-    const T* vcol = I.V + (l < p ? l : p - 1) * I.ldv;
-    acc_t acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    // the trip count is the same for every lane (MFMA is a whole-wave
-    // operation); covariates at or past n read as zero
-    for (int64_t k0 = 0; k0 < n; k0 += 16) {
-      const int64_t k = k0 + 4 * g;
-      Quad<T> v;
-      quad_at<T, VEC>(v, vcol, k, n);
-      Quad<T> a[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        quad_at<T, VEC>(a[t], acol[t], k, n);
-        if (!aok[t]) zero4(a[t]);
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::mac(v.e[s], a[t].e[s], acc[t]);
-    }
-    // epilogue: acc[t][v] = z at l = 16 b + row(g, v), column col0 + 16 t + c.
-    // w = nu z^(d-1) in the storage precision (the exponent loop outside, so
-    // that the products are independent), the sums of w z in fp64
     T nl[4];   // clamped loads without branches, issued together
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -101,7 +114,7 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
     for (int t = 0; t < NT; ++t) zp[t] = acc_t{1, 1, 1, 1};
     for (int e = 0; e < dm1; ++e)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) zp[t] *= acc[t];
+      for (int t = 0; t < NT; ++t) zp[t] *= acc[q][t];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       Quad<T> wq;
@@ -109,7 +122,7 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
       for (int v = 0; v < 4; ++v) {
         const T wv = nl[v] * zp[t][v];
         wq.e[v] = wv;
-        wsum[t] += (double)wv * (double)acc[t][v];
+        wsum[t] += (double)wv * (double)acc[q][t][v];
       }
       vstore4(I.Wp + ((b * I.nt + cg * NTM + t) * 64 + lane) * 4, wq);
     }

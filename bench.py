@@ -51,9 +51,9 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
                    "paper_1911_03813_amd/csrc/kcommon.hpp", "paper_1911_03813_amd/csrc/lp_kernels.hip",
                    "paper_1911_03813_amd/csrc/lp.hpp")
-TRAFFIC_SHA = "95f498bce3009574"
-TRAFFIC_BYTES = {("fp32", "gemm1"): 506.7e6, ("fp32", "gemm2"): 474.3e6,
-                 ("fp64", "gemm1"): 1185.1e6, ("fp64", "gemm2"): 948.5e6,
+TRAFFIC_SHA = "d03cd2313759c18a"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 506.6e6, ("fp32", "gemm2"): 475.3e6,
+                 ("fp64", "gemm1"): 1094.2e6, ("fp64", "gemm2"): 948.5e6,
                  ("fp16", "gemm1"): 269.6e6, ("fp16", "gemm2"): 237.5e6,
                  ("bf16x3", "gemm1"): 501.7e6, ("bf16x3", "gemm2"): 460.1e6}
 

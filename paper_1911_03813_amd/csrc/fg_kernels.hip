@@ -629,7 +629,6 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_final(FinalArgs<T> a) {
   __shared__ double sc[FINAL_K][FINAL_COLS + 1];
   __shared__ double sm[FINAL_THREADS];
   const int64_t b = blockIdx.x;
-  const int64_t ncol = (int64_t)a.ng * a.r;
   if (b < a.ntile) {
     const int64_t nrb = (a.n + 63) / 64;
     const int64_t i0 = (b % nrb) * 64;

@@ -319,7 +319,7 @@ def served_leg(S, ctx, count, rate):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the evaluation would shard over observations with one all-reduce of Y and w).",
               file=sys.stderr)
         sys.exit(2)

@@ -430,9 +430,9 @@ class GroupEngine {
     launch_gmodel<T>(n_gm_, st_, d_ginst_, d_items_ + off_gm_);
     launch_ggemm2<T>(true, n_g2_, st_, d_ginst_, d_items_ + off_g2_);
     launch_gfinal<T>(n_gf_, st_, d_ginst_, d_items_ + off_gf_);
-    launch_lb_dots<T>(nbmax_, nlanes_, st_, d_lanes_);
+    launch_lb_dots<T>(nbmax_, nlanes_, st_, d_lanes_, d_lbitems_, n_lbi_);
     launch_lb_step<T>(nlanes_, st_, d_lanes_, LbParams{nullptr});
-    launch_lb_apply<T>(nbmax_, nlanes_, st_, d_lanes_);
+    launch_lb_apply<T>(nbmax_, nlanes_, st_, d_lanes_, d_lbitems_, n_lbi_);
   }
 
   // descriptor, item and lane tables of `set` into the table buffer
@@ -444,6 +444,7 @@ class GroupEngine {
     std::vector<int> done0;
     const int NTM = sizeof(T) == 8 ? GG_NT_F64 : GG_NT_F32;
     std::vector<GItem> g1, gm, g2, gf;
+    std::vector<LbItem> lbi;   // (lane, chunk) blocks of the dot and apply kernels
     nbmax_ = 1;
     for (size_t i = 0; i < set.size(); ++i) {
       EngineInst<T>* I = set[i];
@@ -460,6 +461,7 @@ class GroupEngine {
       for (int k = 0; k < I->R; ++k) {
         LbLane<T> L = I->lanes[k];
         L.inst = (int)i;
+        for (int b = 0; b < L.nb; ++b) lbi.push_back({(int)lanes.size(), b});
         lanes.push_back(L);
         done0.push_back(0);
         nbmax_ = std::max(nbmax_, L.nb);
@@ -474,13 +476,15 @@ class GroupEngine {
     items.insert(items.end(), g2.begin(), g2.end());
     items.insert(items.end(), gf.begin(), gf.end());
     nlanes_ = (int)lanes.size();
-    // table buffer: [ginst][seeds][items][lanes][lane_done]
+    n_lbi_ = (int)lbi.size();
+    // table buffer: [ginst][seeds][items][lanes][lane_done][lane chunks]
     Carver c(nullptr);
     c.take<GInst<T>>(gi.size() + 1);
     c.take<uint64_t>(seeds.size() + 1);
     c.take<GItem>(items.size() + 1);
     c.take<LbLane<T>>(lanes.size() + 1);
     c.take<int>(lanes.size() + 1);
+    c.take<LbItem>(lbi.size() + 1);
     const size_t need = c.off + 256;
     hipError_t e;
     if (need > tab_bytes_) {
@@ -502,6 +506,7 @@ class GroupEngine {
     d_items_ = t.take<GItem>(items.size() + 1);
     d_lanes_ = t.take<LbLane<T>>(lanes.size() + 1);
     d_lane_done_ = t.take<int>(lanes.size() + 1);
+    d_lbitems_ = t.take<LbItem>(lbi.size() + 1);
     for (size_t L = 0; L < lanes.size(); ++L) lanes[L].done_flag = d_lane_done_ + L;
     // every flag starts low in a new table: a lane that has stopped raises
     // its flag again at each step (its state is final), so nothing is lost
@@ -514,6 +519,8 @@ class GroupEngine {
                                               st_)) != hipSuccess) ||
         (e = hipMemcpyAsync(d_lanes_, lanes.data(), sizeof(LbLane<T>) * lanes.size(), hipMemcpyHostToDevice, st_)) != hipSuccess ||
         (e = hipMemcpyAsync(d_lane_done_, done0.data(), sizeof(int) * done0.size(), hipMemcpyHostToDevice, st_)) != hipSuccess ||
+        (lbi.size() && (e = hipMemcpyAsync(d_lbitems_, lbi.data(), sizeof(LbItem) * lbi.size(), hipMemcpyHostToDevice,
+                                            st_)) != hipSuccess) ||
         (e = hipStreamSynchronize(st_)) != hipSuccess)
       return ctx_->hip_fail(e, "engine table upload");
     return SYMTD_OK;
@@ -550,8 +557,9 @@ class GroupEngine {
   GItem* d_items_ = nullptr;
   LbLane<T>* d_lanes_ = nullptr;
   int* d_lane_done_ = nullptr;
+  LbItem* d_lbitems_ = nullptr;
   int off_g1_ = 0, n_g1_ = 0, off_gm_ = 0, n_gm_ = 0, off_g2_ = 0, n_g2_ = 0, off_gf_ = 0, n_gf_ = 0;
-  int nlanes_ = 0, nbmax_ = 1;
+  int nlanes_ = 0, nbmax_ = 1, n_lbi_ = 0;
   std::vector<int> lane_done_host_;
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;

@@ -24,7 +24,7 @@
 namespace symtd {
 
 constexpr int LB_MMAX = 8;            // largest L-BFGS memory
-constexpr int LB_CHUNK = 2048;        // vector elements per block of the dot/apply kernels
+constexpr int LB_CHUNK = 1024;        // vector elements per block of the dot/apply kernels
 // inner products computed per lane and evaluation (see k_lb_dots)
 constexpr int LB_GTGT = 0, LB_GTD = 1, LB_YTYT = 2, LB_YTD = 3, LB_YTGT = 4, LB_MAXG = 5;
 constexpr int LB_GTS = 6, LB_GTY = LB_GTS + LB_MMAX, LB_SYT = LB_GTY + LB_MMAX, LB_YYT = LB_SYT + LB_MMAX;
@@ -78,12 +78,20 @@ struct LbState {
   double YY[LB_MMAX][LB_MMAX];
 };
 
+// A block of the dot and apply kernels: chunk `blk` of lane `lane`.  With a
+// list of them (the grouped engine), only the chunks the lanes have are
+// launched; without one the grid is (largest chunk count) x lanes and blocks
+// past a lane's own count return at once.
+struct LbItem { int lane, blk; };
+
 template <typename T>
-void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev);
+void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev,
+                    const LbItem* items = nullptr, int nitems = 0);
 template <typename T>
 void launch_lb_step(int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbParams& prm);
 template <typename T>
-void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev);
+void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev,
+                     const LbItem* items = nullptr, int nitems = 0);
 
 // Starts.  Gaussian: A_0 columns of normals (stream 1) into x; RRF: Omega
 // (stream 2) into the packed layout of the second product.  Then column

@@ -73,10 +73,14 @@ __device__ __forceinline__ double wave_max(double v) {
 // as per-block partials (fixed order: thread-strided, then a fixed tree).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_lb_dots(const LbLane<T>* lanes) {
-  const int L = blockIdx.y;
+__global__ __launch_bounds__(256) void k_lb_dots(const LbLane<T>* lanes, const LbItem* items) {
+  int L = blockIdx.y, b = blockIdx.x;
+  if (items) {
+    const LbItem it = items[blockIdx.x];
+    L = it.lane;
+    b = it.blk;
+  }
   const LbLane<T> ln = lanes[L];
-  const int b = blockIdx.x;
   if (b >= ln.nb) return;
   const int phase = ln.state->phase;
   if (phase == LB_DONE) return;
@@ -401,10 +405,14 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbParams
 // point (or, when it has finished, its final point) into the evaluation inputs
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes) {
-  const int L = blockIdx.y;
+__global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes, const LbItem* items) {
+  int L = blockIdx.y, b = blockIdx.x;
+  if (items) {
+    const LbItem it = items[blockIdx.x];
+    L = it.lane;
+    b = it.blk;
+  }
   const LbLane<T> ln = lanes[L];
-  const int b = blockIdx.x;
   if (b >= ln.nb) return;
   const LbState& s = *ln.state;
   const int act = s.action;
@@ -632,16 +640,26 @@ __global__ __launch_bounds__(256) void k_grrf_finish(const LbLane<T>* lanes, con
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev) {
-  hipLaunchKernelGGL(k_lb_dots<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev);
+void launch_lb_dots(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbItem* items,
+                    int nitems) {
+  if (items) {
+    if (nitems > 0) hipLaunchKernelGGL(k_lb_dots<T>, dim3(nitems), dim3(256), 0, st, lanes_dev, items);
+  } else {
+    hipLaunchKernelGGL(k_lb_dots<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev, items);
+  }
 }
 template <typename T>
 void launch_lb_step(int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbParams& prm) {
   hipLaunchKernelGGL(k_lb_step<T>, dim3(lanes), dim3(64), 0, st, lanes_dev, prm);
 }
 template <typename T>
-void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev) {
-  hipLaunchKernelGGL(k_lb_apply<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev);
+void launch_lb_apply(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev, const LbItem* items,
+                     int nitems) {
+  if (items) {
+    if (nitems > 0) hipLaunchKernelGGL(k_lb_apply<T>, dim3(nitems), dim3(256), 0, st, lanes_dev, items);
+  } else {
+    hipLaunchKernelGGL(k_lb_apply<T>, dim3(nbmax, lanes), dim3(256), 0, st, lanes_dev, items);
+  }
 }
 template <typename T>
 void launch_init_gauss(int nbmax, int lanes, hipStream_t st, const LbLane<T>* lanes_dev) {
@@ -672,9 +690,9 @@ void launch_rrf_finish(int lanes, int r, hipStream_t st, const LbLane<T>* lanes_
 }
 
 #define SYMTD_LB_INST(T)                                                                                       \
-  template void launch_lb_dots<T>(int, int, hipStream_t, const LbLane<T>*);                                    \
+  template void launch_lb_dots<T>(int, int, hipStream_t, const LbLane<T>*, const LbItem*, int);                \
   template void launch_lb_step<T>(int, hipStream_t, const LbLane<T>*, const LbParams&);                         \
-  template void launch_lb_apply<T>(int, int, hipStream_t, const LbLane<T>*);                                    \
+  template void launch_lb_apply<T>(int, int, hipStream_t, const LbLane<T>*, const LbItem*, int);               \
   template void launch_init_gauss<T>(int, int, hipStream_t, const LbLane<T>*);                                  \
   template void launch_init_given<T>(int, int, hipStream_t, const LbLane<T>*);                                  \
   template void launch_norm_cols<T>(int, int, hipStream_t, const LbLane<T>*);                                   \

@@ -263,6 +263,9 @@ __global__ __launch_bounds__(64) void k_ggemm2(const GInst<T>* insts, const GIte
 // ---------------------------------------------------------------------------
 constexpr int GM_RMAX = 32;
 constexpr int GM_ROWS = 64;
+// partials (of w per tile, of Y per split) one thread loads at once: p = 8192
+// observations make 32 tiles and 32 splits of 256
+constexpr int GF_SPLITS = 32;
 
 // the chunk of rows [i0, i0 + GM_ROWS) of A (r <= GM_RMAX columns) into
 // sA[ii][l] as fp64 (times lambda_l when lam is given), zero past n
@@ -307,19 +310,26 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
     // GM_RMAX^2 / 256 of them
     constexpr int PP = GM_RMAX * GM_RMAX / 256;
     double s[PP];
+    int jq[PP], lq[PP];   // the pairs; pairs outside the model read column 0 and are not written
 #pragma unroll
-    for (int q = 0; q < PP; ++q) s[q] = 0.0;
+    for (int q = 0; q < PP; ++q) {
+      s[q] = 0.0;
+      const int e = threadIdx.x + 256 * q;
+      const int j = e % GM_RMAX, l = e / GM_RMAX;
+      const bool ok = j < r && l < r && j <= l;
+      jq[q] = ok ? j : 0;
+      lq[q] = ok ? l : 0;
+    }
     for (int64_t i0 = 0; i0 < n; i0 += GM_ROWS) {
       gm_stage(A, I.lda, n, r, i0, nullptr, sA);
       __syncthreads();
       const int rows = (int)min((int64_t)GM_ROWS, n - i0);
+      // every pair advances in the same row loop (independent chains, no
+      // per-thread branch), each summing over the rows in order
+#pragma unroll 4
+      for (int ii = 0; ii < rows; ++ii)
 #pragma unroll
-      for (int q = 0; q < PP; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        const int j = e % GM_RMAX, l = e / GM_RMAX;
-        if (j < r && l < r && j <= l)
-          for (int ii = 0; ii < rows; ++ii) s[q] = fma(sA[ii][j], sA[ii][l], s[q]);
-      }
+        for (int q = 0; q < PP; ++q) s[q] = fma(sA[ii][jq[q]], sA[ii][lq[q]], s[q]);
       __syncthreads();
     }
 #pragma unroll
@@ -357,14 +367,14 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
     double u = 0.0;
     for (int l = 0; l < r; ++l) u += Bs[(int64_t)l * r + j] * Cs[(int64_t)l * r + j] * lam[l];
     const int col = k * r + j;
-    // the tile partials of w, loaded eight at a time from valid rows
+    // the tile partials of w, up to GF_SPLITS at a time from valid rows, in order
     double w = 0.0;
-    for (int t0 = 0; t0 < I.ntile; t0 += 8) {
-      double v[8];
+    for (int t0 = 0; t0 < I.ntile; t0 += GF_SPLITS) {
+      double v[GF_SPLITS];
 #pragma unroll
-      for (int h = 0; h < 8; ++h) v[h] = I.wpart[(int64_t)min(t0 + h, I.ntile - 1) * I.cols + col];
+      for (int h = 0; h < GF_SPLITS; ++h) v[h] = I.wpart[(int64_t)min(t0 + h, I.ntile - 1) * I.cols + col];
 #pragma unroll
-      for (int h = 0; h < 8; ++h)
+      for (int h = 0; h < GF_SPLITS; ++h)
         if (t0 + h < I.ntile) w += v[h];
     }
     I.glam[col] = -2.0 * (w - u);
@@ -373,8 +383,9 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
   fs[threadIdx.x] = fsh;
   __syncthreads();
   if (threadIdx.x == 0) {
+    // shares past thread r - 1 are zero
     double f = 0.0;
-    for (int t = 0; t < 256; ++t) f += fs[t];
+    for (int t = 0; t < min(r, 256); ++t) f += fs[t];
     I.f[k] = I.alpha + f;
   }
   // Y_M = A D_lambda C for this model's columns
@@ -387,6 +398,7 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
       for (int e = threadIdx.x; e < rows * r; e += 256) {
         const int ii = e % rows, j = e / rows;
         double s = 0.0;
+#pragma unroll 4
         for (int l = 0; l < r; ++l) s = fma(sA[ii][l], sC[j * r + l], s);
         I.YM[((int64_t)k * r + j) * n + i0 + ii] = s;
       }
@@ -412,17 +424,20 @@ __global__ __launch_bounds__(256) void k_gfinal(const GInst<T>* insts, const GIt
   const int64_t rp = (int64_t)I.nt * 16;
   const double lj = I.lam[col];
   for (int i = threadIdx.x; i < I.n; i += 256) {
-    // the split partials, loaded eight at a time from valid splits, summed in order
+    const double ym = I.YM[(int64_t)col * I.n + i];
+    // the split partials (at most GF_SPLITS per round, from valid splits, all
+    // in flight together), summed in split order
     double y = 0.0;
-    for (int s0 = 0; s0 < I.nsplit; s0 += 8) {
-      T v[8];
+    for (int s0 = 0; s0 < I.nsplit; s0 += GF_SPLITS) {
+      T v[GF_SPLITS];
 #pragma unroll
-      for (int h = 0; h < 8; ++h) v[h] = I.Ypart[((int64_t)min(s0 + h, I.nsplit - 1) * rp + col) * I.ldy + i];
+      for (int h = 0; h < GF_SPLITS; ++h)
+        v[h] = I.Ypart[((int64_t)min(s0 + h, I.nsplit - 1) * rp + col) * I.ldy + i];
 #pragma unroll
-      for (int h = 0; h < 8; ++h)
+      for (int h = 0; h < GF_SPLITS; ++h)
         if (s0 + h < I.nsplit) y += (double)v[h];
     }
-    const double gval = -2.0 * I.d * (y - I.YM[(int64_t)col * I.n + i]) * lj;
+    const double gval = -2.0 * I.d * (y - ym) * lj;
     I.G[(int64_t)col * I.ldg + i] = (T)gval;
   }
 }

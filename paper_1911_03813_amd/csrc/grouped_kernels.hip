@@ -106,7 +106,7 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t lv = 16 * b + Mfma<T>::row(g, v);
-      const double x = I.nu[lv < p ? lv : p - 1];
+      const double x = gload(I.nu + (lv < p ? lv : p - 1));
       nl[v] = lv < p ? (T)x : T(0);
     }
     acc_t zp[NT];
@@ -139,7 +139,7 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
   for (int e = threadIdx.x; e < NT * 16; e += 256) {
     const int col = col0 + e;
     if (col < I.cols)
-      I.wpart[(int64_t)tile * I.cols + col] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+      gstore(I.wpart + (int64_t)tile * I.cols + col, (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]));
   }
 }
 
@@ -279,7 +279,7 @@ __device__ __forceinline__ void gm_stage(const T* A, int64_t lda, int n, int r, 
     const int e = threadIdx.x + 256 * it;
     const int ii = e % GM_ROWS, l = min(e / GM_ROWS, r - 1);
     const int64_t i = i0 + ii;
-    x[it] = A[(int64_t)l * lda + (i < n ? i : 0)];
+    x[it] = gload(A + (int64_t)l * lda + (i < n ? i : 0));
   }
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
     for (int t0 = 0; t0 < I.ntile; t0 += GF_SPLITS) {
       double v[GF_SPLITS];
 #pragma unroll
-      for (int h = 0; h < GF_SPLITS; ++h) v[h] = I.wpart[(int64_t)min(t0 + h, I.ntile - 1) * I.cols + col];
+      for (int h = 0; h < GF_SPLITS; ++h) v[h] = gload(I.wpart + (int64_t)min(t0 + h, I.ntile - 1) * I.cols + col);
 #pragma unroll
       for (int h = 0; h < GF_SPLITS; ++h)
         if (t0 + h < I.ntile) w += v[h];
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
         double s = 0.0;
 #pragma unroll 4
         for (int l = 0; l < r; ++l) s = fma(sA[ii][l], sC[j * r + l], s);
-        I.YM[((int64_t)k * r + j) * n + i0 + ii] = s;
+        gstore(I.YM + ((int64_t)k * r + j) * n + i0 + ii, s);
       }
     }
   } else {
@@ -422,9 +422,9 @@ __global__ __launch_bounds__(256) void k_gfinal(const GInst<T>* insts, const GIt
   const GInst<T> I = insts[it.inst];
   const int col = it.a;
   const int64_t rp = (int64_t)I.nt * 16;
-  const double lj = I.lam[col];
+  const double lj = gload(I.lam + col);
   for (int i = threadIdx.x; i < I.n; i += 256) {
-    const double ym = I.YM[(int64_t)col * I.n + i];
+    const double ym = gload(I.YM + (int64_t)col * I.n + i);
     // the split partials (at most GF_SPLITS per round, from valid splits, all
     // in flight together), summed in split order
     double y = 0.0;
@@ -432,13 +432,13 @@ __global__ __launch_bounds__(256) void k_gfinal(const GInst<T>* insts, const GIt
       T v[GF_SPLITS];
 #pragma unroll
       for (int h = 0; h < GF_SPLITS; ++h)
-        v[h] = I.Ypart[((int64_t)min(s0 + h, I.nsplit - 1) * rp + col) * I.ldy + i];
+        v[h] = gload(I.Ypart + ((int64_t)min(s0 + h, I.nsplit - 1) * rp + col) * I.ldy + i);
 #pragma unroll
       for (int h = 0; h < GF_SPLITS; ++h)
         if (s0 + h < I.nsplit) y += (double)v[h];
     }
     const double gval = -2.0 * I.d * (y - ym) * lj;
-    I.G[(int64_t)col * I.ldg + i] = (T)gval;
+    gstore(I.G + (int64_t)col * I.ldg + i, (T)gval);
   }
 }
 

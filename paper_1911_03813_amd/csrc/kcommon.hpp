@@ -41,22 +41,34 @@ template <> struct Mfma<double> {
 // Four consecutive elements of a column held by one lane.
 template <typename T> struct Quad { T e[4]; };
 
+// Global-memory accesses.  Every buffer the helpers below read or write is
+// in global memory, but a pointer that a kernel reads out of a descriptor
+// (rather than receiving as an argument) is otherwise accessed with flat
+// instructions, whose waits also cover LDS and scalar loads.  T must be a
+// scalar or a clang vector type.
+typedef double v2d __attribute__((ext_vector_type(2)));
+template <typename T> using global_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) { return *(const global_t<T>*)p; }
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, const T v) { *(global_t<T>*)p = v; }
+
 // 16-byte-aligned vector load of 4 consecutive elements.
 __device__ __forceinline__ void vload4(Quad<float>& q, const float* p) {
-  const float4 t = *reinterpret_cast<const float4*>(p);
-  q.e[0] = t.x; q.e[1] = t.y; q.e[2] = t.z; q.e[3] = t.w;
+  const v4f t = gload(reinterpret_cast<const v4f*>(p));
+  q.e[0] = t[0]; q.e[1] = t[1]; q.e[2] = t[2]; q.e[3] = t[3];
 }
 __device__ __forceinline__ void vload4(Quad<double>& q, const double* p) {
-  const double2 t0 = *reinterpret_cast<const double2*>(p);
-  const double2 t1 = *reinterpret_cast<const double2*>(p + 2);
-  q.e[0] = t0.x; q.e[1] = t0.y; q.e[2] = t1.x; q.e[3] = t1.y;
+  const v2d t0 = gload(reinterpret_cast<const v2d*>(p));
+  const v2d t1 = gload(reinterpret_cast<const v2d*>(p + 2));
+  q.e[0] = t0[0]; q.e[1] = t0[1]; q.e[2] = t1[0]; q.e[3] = t1[1];
 }
 __device__ __forceinline__ void vstore4(float* p, const Quad<float>& q) {
-  *reinterpret_cast<float4*>(p) = make_float4(q.e[0], q.e[1], q.e[2], q.e[3]);
+  gstore(reinterpret_cast<v4f*>(p), v4f{q.e[0], q.e[1], q.e[2], q.e[3]});
 }
 __device__ __forceinline__ void vstore4(double* p, const Quad<double>& q) {
-  *reinterpret_cast<double2*>(p) = make_double2(q.e[0], q.e[1]);
-  *reinterpret_cast<double2*>(p + 2) = make_double2(q.e[2], q.e[3]);
+  gstore(reinterpret_cast<v2d*>(p), v2d{q.e[0], q.e[1]});
+  gstore(reinterpret_cast<v2d*>(p + 2), v2d{q.e[2], q.e[3]});
 }
 
 template <typename T>
@@ -74,7 +86,7 @@ __device__ __forceinline__ void load4(Quad<T>& q, const T* base, int64_t i, int6
     if (ok) vload4(q, base + i); else zero4(q);
   } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) q.e[e] = (ok && i + e < n) ? base[i + e] : T(0);
+    for (int e = 0; e < 4; ++e) q.e[e] = (ok && i + e < n) ? gload(base + i + e) : T(0);
   }
 }
 
@@ -85,7 +97,7 @@ __device__ __forceinline__ void load_full(Quad<T>& q, const T* p) {
   if constexpr (VEC) {
     vload4(q, p);
   } else {
-    q.e[0] = p[0]; q.e[1] = p[1]; q.e[2] = p[2]; q.e[3] = p[3];
+    q.e[0] = gload(p); q.e[1] = gload(p + 1); q.e[2] = gload(p + 2); q.e[3] = gload(p + 3);
   }
 }
 
@@ -96,7 +108,7 @@ template <typename T>
 __device__ __forceinline__ void load_tail(Quad<T>& q, const T* col, int64_t i, int64_t n) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const T x = col[min(i + e, n - 1)];
+    const T x = gload(col + min(i + e, n - 1));
     q.e[e] = (i + e < n) ? x : T(0);
   }
 }

@@ -42,15 +42,15 @@ enum { EX_PGTOL = 1, EX_FTOL = 2, EX_MAX_ITERS = 3, EX_MAX_EVALS = 4, EX_LINESEA
 template <typename T>
 __device__ __forceinline__ double trial_grad(const LbLane<T>& ln, int64_t e) {
   const bool lam = e < ln.r;
-  const double a = ln.glam_t[lam ? e : ln.r - 1];
-  const double b = (double)ln.G_t[lam ? 0 : e - ln.r];
+  const double a = gload(ln.glam_t + (lam ? e : ln.r - 1));
+  const double b = (double)gload(ln.G_t + (lam ? 0 : e - ln.r));
   return (lam ? a : b) / ln.scale;
 }
 
 template <typename T>
 __device__ __forceinline__ void write_trial(const LbLane<T>& ln, int64_t e, double xt) {
-  if (e < ln.r) ln.lam_t[e] = xt;
-  else ln.A_t[e - ln.r] = (T)xt;
+  if (e < ln.r) gstore(ln.lam_t + e, xt);
+  else gstore(ln.A_t + (e - ln.r), (T)xt);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_lb_dots(const LbLane<T>* lanes, const L
     const int64_t e = (int64_t)b * LB_CHUNK + k * 256 + threadIdx.x;
     if (e >= ln.N) break;
     const double gt = trial_grad(ln, e);
-    const double ge = ln.g[e], de = ln.d[e];
+    const double ge = gload(ln.g + e), de = gload(ln.d + e);
     const double yt = gt - ge;
     acc[LB_GTGT] = fma(gt, gt, acc[LB_GTGT]);
     acc[LB_GTD] = fma(gt, de, acc[LB_GTD]);
@@ -107,8 +107,8 @@ __global__ __launch_bounds__(256) void k_lb_dots(const LbLane<T>* lanes, const L
 #pragma unroll
     for (int s = 0; s < LB_MMAX; ++s) {
       const int64_t sq = s < cnt ? s : 0;
-      Sv[s] = ln.S[sq * ln.N + e];
-      Yv[s] = ln.Y[sq * ln.N + e];
+      Sv[s] = gload(ln.S + sq * ln.N + e);
+      Yv[s] = gload(ln.Y + sq * ln.N + e);
     }
 #pragma unroll
     for (int s = 0; s < LB_MMAX; ++s) {
@@ -425,37 +425,37 @@ __global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes, const 
   for (int k = 0; k < LB_CHUNK / 256; ++k) {
     const int64_t e = (int64_t)b * LB_CHUNK + k * 256 + threadIdx.x;
     if (e >= ln.N) break;
-    double xe = ln.x[e];
+    double xe = gload(ln.x + e);
     double xt;
     if (act == LB_START_DIR) {
       const double gt = trial_grad(ln, e);
-      ln.g[e] = gt;
-      ln.d[e] = -gt;
+      gstore(ln.g + e, gt);
+      gstore(ln.d + e, -gt);
       xt = xe + a * (-gt);
     } else if (act == LB_TRIAL) {
-      xt = xe + a * ln.d[e];
+      xt = xe + a * gload(ln.d + e);
     } else if (act == LB_ACCEPT_DIR || act == LB_ACCEPT_FINAL) {
-      const double de = ln.d[e];
-      const double gold = ln.g[e];
+      const double de = gload(ln.d + e);
+      const double gold = gload(ln.g + e);
       const double gt = trial_grad(ln, e);
       xe = xe + a_acc * de;
-      ln.x[e] = xe;
-      ln.g[e] = gt;
+      gstore(ln.x + e, xe);
+      gstore(ln.g + e, gt);
       if (act == LB_ACCEPT_FINAL) {
         xt = xe;
       } else {
         const double snew = a_acc * de, ynew = gt - gold;
         if (store) {
-          ln.S[(int64_t)slot * ln.N + e] = snew;
-          ln.Y[(int64_t)slot * ln.N + e] = ynew;
+          gstore(ln.S + (int64_t)slot * ln.N + e, snew);
+          gstore(ln.Y + (int64_t)slot * ln.N + e, ynew);
         }
         // every slot read (unused ones from a valid slot) before any is used
         double Sv[LB_MMAX], Yv[LB_MMAX];
 #pragma unroll
         for (int q = 0; q < LB_MMAX; ++q) {
           const int64_t sq = q < cnt ? q : 0;
-          Sv[q] = ln.S[sq * ln.N + e];
-          Yv[q] = ln.Y[sq * ln.N + e];
+          Sv[q] = gload(ln.S + sq * ln.N + e);
+          Yv[q] = gload(ln.Y + sq * ln.N + e);
         }
         double dn = coef_g * gt;
 #pragma unroll
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void k_lb_apply(const LbLane<T>* lanes, const 
             dn = fma(cs[q], Sq, fma(cy[q], Yq, dn));
           }
         }
-        ln.d[e] = dn;
+        gstore(ln.d + e, dn);
         xt = xe + a * dn;
       }
     } else {   // LB_RESTORE

@@ -209,9 +209,8 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
   constexpr int PL = S::PL;
   constexpr int KCH = lp_chunk(KIND);
   constexpr int PART = LP_WAVES * LP_MT * NT * 256;
-  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256], lx2[LP_STAGES > 2 ? S::XP * 256 : 1];
-  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256], ly2[LP_STAGES > 2 ? S::YP * 256 : 1];
-  LP_CHUNK_LOOP
+  __shared__ u4 lx0[S::XP * 256], lx1[S::XP * 256];
+  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, c = lane & 15;

@@ -235,15 +235,15 @@ class GroupEngine {
     }
     // alpha of every new instance
     std::vector<double> alphas(batch.size(), 0.0);
-    bool any = false;
+    std::vector<NormXJob<T>> jobs;
     for (auto* I : batch)
-      if (I->o.alpha_mode == SYMTD_ALPHA_COMPUTE) {
-        symtd_status s = run_normx<T>(ctx_, st_, I->g.V, I->ld, I->g.nu, I->n, I->p, I->pb.d, I->alpha_dev);
-        if (s != SYMTD_OK) return s;
-        any = true;
-      }
+      if (I->o.alpha_mode == SYMTD_ALPHA_COMPUTE)
+        jobs.push_back(NormXJob<T>{I->g.V, I->ld, I->g.nu, I->n, I->p, I->pb.d, I->alpha_dev});
+    const bool any = !jobs.empty();
     if (any) {
-      if ((e = hipStreamSynchronize(st_)) != hipSuccess) return ctx_->hip_fail(e, "engine alpha");
+      // every new instance's alpha in one grouped launch (synchronised on return)
+      symtd_status s = run_normx_grouped<T>(ctx_, st_, jobs);
+      if (s != SYMTD_OK) return s;
       for (size_t i = 0; i < batch.size(); ++i)
         if (batch[i]->o.alpha_mode == SYMTD_ALPHA_COMPUTE &&
             (e = hipMemcpy(&alphas[i], batch[i]->alpha_dev, sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)

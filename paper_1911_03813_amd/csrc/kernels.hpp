@@ -153,4 +153,18 @@ void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<float>& a
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<double>& a);
 void launch_reduce(hipStream_t st, const ReduceArgs& a);
 
+// ||X||^2 of several data sets in one launch (vector loads: 16-byte aligned
+// V, leading dimension a multiple of 16 bytes): block b forms tile pair
+// items[b].pair of set items[b].set into that set's partials; then one block
+// per set sums its partials in the same order as launch_reduce.
+struct NormXItem { int set; int pair; };
+template <typename S>
+struct GNormX {
+  NormXArgs<S> a;     // a.part: this set's partials
+  int64_t pairs;      // ntile (ntile + 1) / 2
+  double* alpha;
+};
+void launch_normx_grouped(int nitems, int nsets, hipStream_t st, const GNormX<float>* sets, const NormXItem* items);
+void launch_normx_grouped(int nitems, int nsets, hipStream_t st, const GNormX<double>* sets, const NormXItem* items);
+
 }  // namespace symtd

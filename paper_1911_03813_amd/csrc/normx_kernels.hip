@@ -24,14 +24,15 @@ __device__ __forceinline__ void tri_pair(int64_t b, int64_t T, int64_t& tr, int6
   tc = t + (b - start(t));
 }
 
+// tile pair b of data set a, weighted, into *out (a whole block of 256 threads)
 template <typename S, bool VEC>
-__global__ __launch_bounds__(256) void k_normx(NormXArgs<S> a) {
+__device__ __forceinline__ void normx_pair(const NormXArgs<S>& a, int64_t b, double* out) {
   using acc_t = v4d;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int g = lane >> 4, c = lane & 15;
   int64_t tr, tc;
-  tri_pair(blockIdx.x, a.ntile, tr, tc);
+  tri_pair(b, a.ntile, tr, tc);
   const int64_t rbase = tr * 128 + (wave >> 1) * 64;
   const int64_t cbase = tc * 128 + (wave & 1) * 64;
 
@@ -94,21 +95,42 @@ __global__ __launch_bounds__(256) void k_normx(NormXArgs<S> a) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const double w = (tr == tc) ? 1.0 : 2.0;
-    a.part[blockIdx.x] = w * (((red[0] + red[1]) + red[2]) + red[3]);
+    *out = w * (((red[0] + red[1]) + red[2]) + red[3]);
   }
 }
 
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+template <typename S, bool VEC>
+__global__ __launch_bounds__(256) void k_normx(NormXArgs<S> a) {
+  normx_pair<S, VEC>(a, blockIdx.x, a.part + blockIdx.x);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_gnormx(const GNormX<S>* sets, const NormXItem* items) {
+  const NormXItem it = items[blockIdx.x];
+  const NormXArgs<S> a = sets[it.set].a;
+  normx_pair<S, true>(a, it.pair, a.part + it.pair);
+}
+
+// the partials of one set summed: thread-strided, then a fixed tree
+__device__ __forceinline__ void reduce_body(const double* part, int64_t count, double* out) {
   __shared__ double s[256];
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < a.count; e += 256) acc += a.part[e];
+  for (int64_t e = threadIdx.x; e < count; e += 256) acc += part[e];
   s[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.out[0] = s[0];
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) { reduce_body(a.part, a.count, a.out); }
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_greduce(const GNormX<S>* sets) {
+  const GNormX<S> g = sets[blockIdx.x];
+  reduce_body(g.a.part, g.pairs, g.alpha);
 }
 
 void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<float>& a) {
@@ -121,6 +143,19 @@ void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<double>& 
 }
 void launch_reduce(hipStream_t st, const ReduceArgs& a) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, a);
+}
+template <typename S>
+static void launch_normx_grouped_t(int nitems, int nsets, hipStream_t st, const GNormX<S>* sets,
+                                   const NormXItem* items) {
+  if (nitems <= 0 || nsets <= 0) return;
+  hipLaunchKernelGGL(k_gnormx<S>, dim3(nitems), dim3(256), 0, st, sets, items);
+  hipLaunchKernelGGL(k_greduce<S>, dim3(nsets), dim3(256), 0, st, sets);
+}
+void launch_normx_grouped(int nitems, int nsets, hipStream_t st, const GNormX<float>* sets, const NormXItem* items) {
+  launch_normx_grouped_t(nitems, nsets, st, sets, items);
+}
+void launch_normx_grouped(int nitems, int nsets, hipStream_t st, const GNormX<double>* sets, const NormXItem* items) {
+  launch_normx_grouped_t(nitems, nsets, st, sets, items);
 }
 
 }  // namespace symtd

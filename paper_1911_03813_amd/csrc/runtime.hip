@@ -372,6 +372,67 @@ symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, 
   return SYMTD_OK;
 }
 
+template <typename S>
+symtd_status run_normx_grouped(symtd_ctx* ctx, hipStream_t st, const std::vector<NormXJob<S>>& jobs) {
+  if (jobs.empty()) return SYMTD_OK;
+  const size_t vq = 16 / sizeof(S);
+  bool vec = true;
+  int64_t total = 0;
+  std::vector<int64_t> npairs(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const NormXJob<S>& J = jobs[j];
+    vec = vec && aligned_to<S>(J.V, 16) && (J.ldv % vq) == 0;
+    const int64_t T = (J.p + 127) / 128;
+    npairs[j] = T * (T + 1) / 2;
+    total += npairs[j];
+  }
+  if (!vec || total > 0x7fffffffLL || jobs.size() > 0x7fffffffULL) {
+    // one launch pair per set
+    for (const NormXJob<S>& J : jobs) {
+      symtd_status s = run_normx<S>(ctx, st, J.V, J.ldv, J.nu, J.n, J.p, J.d, J.alpha);
+      if (s != SYMTD_OK) return s;
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    return e == hipSuccess ? SYMTD_OK : ctx->hip_fail(e, "normX sync");
+  }
+  // workspace: [partials][set descriptors][items]
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_part = up((size_t)total * sizeof(double));
+  const size_t b_sets = up(jobs.size() * sizeof(GNormX<S>));
+  const size_t b_items = up((size_t)total * sizeof(NormXItem));
+  symtd_status s = ctx->reserve(b_part + b_sets + b_items);
+  if (s != SYMTD_OK) return s;
+  char* base = (char*)ctx->ws;
+  double* part = (double*)base;
+  GNormX<S>* d_sets = (GNormX<S>*)(base + b_part);
+  NormXItem* d_items = (NormXItem*)(base + b_part + b_sets);
+  std::vector<GNormX<S>> sets(jobs.size());
+  std::vector<NormXItem> items((size_t)total);
+  int64_t off = 0;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const NormXJob<S>& J = jobs[j];
+    sets[j].a = NormXArgs<S>{J.V, J.ldv, J.nu, (int)J.n, (int)J.p, J.d, (J.p + 127) / 128, part + off};
+    sets[j].pairs = npairs[j];
+    sets[j].alpha = J.alpha;
+    for (int64_t b = 0; b < npairs[j]; ++b) items[(size_t)(off + b)] = NormXItem{(int)j, (int)b};
+    off += npairs[j];
+  }
+  hipError_t e;
+  if ((e = hipMemcpyAsync(d_sets, sets.data(), sets.size() * sizeof(GNormX<S>), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(NormXItem), hipMemcpyHostToDevice, st)) !=
+          hipSuccess)
+    return ctx->hip_fail(e, "normX tables");
+  launch_normx_grouped((int)total, (int)jobs.size(), st, d_sets, d_items);
+  if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "kernel launch (grouped normX)");
+  // the host tables above must outlive their copies
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return ctx->hip_fail(e, "normX sync");
+  return SYMTD_OK;
+}
+
+template symtd_status run_normx_grouped<float>(symtd_ctx*, hipStream_t, const std::vector<NormXJob<float>>&);
+template symtd_status run_normx_grouped<double>(symtd_ctx*, hipStream_t, const std::vector<NormXJob<double>>&);
+
 template symtd_status run_normx<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t,
                                        int64_t, int, double*);
 template symtd_status run_normx<double>(symtd_ctx*, hipStream_t, const double*, int64_t, const double*, int64_t,

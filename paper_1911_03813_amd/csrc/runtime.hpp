@@ -86,4 +86,12 @@ template <typename S>
 symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, const double* nu,
                        int64_t n, int64_t p, int d, double* alpha);
 
+// alpha of several data sets, each into its own device fp64 value, in two
+// launches; every value equals what run_normx computes for that set alone.
+// Returns after the stream has finished them.
+template <typename S>
+struct NormXJob { const S* V; int64_t ldv; const double* nu; int64_t n, p; int d; double* alpha; };
+template <typename S>
+symtd_status run_normx_grouped(symtd_ctx* ctx, hipStream_t st, const std::vector<NormXJob<S>>& jobs);
+
 }  // namespace symtd

@@ -158,6 +158,28 @@ def loop_solve(S, ctx, pr):
     return S.symtd_solve(ctx, pr["V"], pr["nu"], pr["d"], pr["r"], **kw)
 
 
+def normx_leg(S, ctx, Vs, nu, d, reps=3):
+    """||X||^2 of the large data set (fp32 storage, fp64 products): time per
+    call and the rate of its algorithmic flop, n p (p + 1) (the p x p Gram
+    matrix's upper triangle with the diagonal, 2 flop per multiply-add)."""
+    import torch
+    n, p = Vs.shape
+    Vd = S.colmajor(torch.from_numpy(np.ascontiguousarray(Vs)).to(torch.float32)).cuda()
+    nud = torch.from_numpy(nu).cuda()
+    a = S.symtd_normX(ctx, Vd, nud, d)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S.symtd_normX(ctx, Vd, nud, d, out=a)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    flop = float(n) * p * (p + 1)
+    peak = PEAK_TFLOPS["fp64"]
+    return {"workload": f"d={d} n={n} p={p}, fp32 storage, fp64 matrix products", "calls": reps,
+            "ms_per_call": t * 1e3, "tflops": flop / t / 1e12, "peak_tflops": peak,
+            "frac": flop / t / 1e12 / peak}
+
+
 def precision_leg(S, ctx, Vs, nu, As, lam, d, steps, warmup):
     """evals/s, product times and error against the fp64 products of every
     product precision on the large workload (fp32 storage for fp32 / fp16 /
@@ -448,6 +470,7 @@ def main():
     del Vd, Ad, out
     if not args.only_fg and args.prec == "fp32":
         res["precisions"] = precision_leg(S, ctx, Vs, nu, As, lam, d, args.steps, args.warmup)
+        res["normx"] = normx_leg(S, ctx, Vs, nu, d)
         if args.batched > 0:
             res["batched"] = batched_leg(S, ctx, args.batched, args.loop_sample)
         if args.served > 0:

@@ -24,6 +24,23 @@ __device__ __forceinline__ void tri_pair(int64_t b, int64_t T, int64_t& tr, int6
   tc = t + (b - start(t));
 }
 
+// Elements i .. i+3 of a column of n (zero past n, and all zero when !ok),
+// without branches.  VEC (16-byte aligned columns, leading dimension a
+// multiple of 4 elements, so a column holds 4 ceil(n/4) elements): one vector
+// load of the quad clamped into the column; otherwise four clamped loads.
+template <typename S, bool VEC>
+__device__ __forceinline__ void nx_load(Quad<S>& q, const S* col, int64_t i, int64_t n, bool ok) {
+  if constexpr (VEC) {
+    const int64_t n4 = (n + 3) & ~(int64_t)3;
+    vload4(q, col + (i < n4 ? i : n4 - 4));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q.e[e] = gload(col + min(i + e, n - 1));
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) q.e[e] = (ok && i + e < n) ? q.e[e] : S(0);
+}
+
 // tile pair b of data set a, weighted, into *out (a whole block of 256 threads)
 template <typename S, bool VEC>
 __device__ __forceinline__ void normx_pair(const NormXArgs<S>& a, int64_t b, double* out) {
@@ -57,8 +74,8 @@ __device__ __forceinline__ void normx_pair(const NormXArgs<S>& a, int64_t b, dou
     const int64_t i = i0 + 4 * g;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      load4<S, VEC>(rq[m], rp[m], i, n, rok[m]);
-      load4<S, VEC>(cq[m], cp[m], i, n, cok[m]);
+      nx_load<S, VEC>(rq[m], rp[m], i, n, rok[m]);
+      nx_load<S, VEC>(cq[m], cp[m], i, n, cok[m]);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)

@@ -357,8 +357,8 @@ symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, 
   symtd_status s = ctx->reserve((size_t)pairs * sizeof(double) + 256);
   if (s != SYMTD_OK) return s;
   double* part = (double*)ctx->ws;
-  const size_t vq = 16 / sizeof(S);
-  const bool vec = aligned_to<S>(V, 16) && (ldv % vq) == 0;
+  // vector loads of clamped quads need whole quads in every column
+  const bool vec = aligned_to<S>(V, 16) && (ldv % 4) == 0;
   NormXArgs<S> a{V, ldv, nu, (int)n, (int)p, d, T, part};
   ctx->prof_begin(4, st);
   launch_normx(vec, dim3((unsigned)pairs), st, a);
@@ -375,13 +375,12 @@ symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, 
 template <typename S>
 symtd_status run_normx_grouped(symtd_ctx* ctx, hipStream_t st, const std::vector<NormXJob<S>>& jobs) {
   if (jobs.empty()) return SYMTD_OK;
-  const size_t vq = 16 / sizeof(S);
   bool vec = true;
   int64_t total = 0;
   std::vector<int64_t> npairs(jobs.size());
   for (size_t j = 0; j < jobs.size(); ++j) {
     const NormXJob<S>& J = jobs[j];
-    vec = vec && aligned_to<S>(J.V, 16) && (J.ldv % vq) == 0;
+    vec = vec && aligned_to<S>(J.V, 16) && (J.ldv % 4) == 0;
     const int64_t T = (J.p + 127) / 128;
     npairs[j] = T * (T + 1) / 2;
     total += npairs[j];

@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void k_gfinal(const GInst<T>* insts, const GIt
   const double lj = gload(I.lam + col);
   for (int i = threadIdx.x; i < I.n; i += 256) {
     const double ym = gload(I.YM + (int64_t)col * I.n + i);
-    // the split partials (at most GF_SPLITS per round, from valid splits, all
+    // the split partials (at most GF_SPLITS per pass, from valid splits, all
     // in flight together), summed in split order
     double y = 0.0;
     for (int s0 = 0; s0 < I.nsplit; s0 += GF_SPLITS) {

@@ -308,28 +308,28 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
   if (fast) {
     // thread t takes the pairs e = t, t + 256, ... (j <= l), at most
     // GM_RMAX^2 / 256 of them
+    // pair q of thread t is e = t + 256 q: j = t mod GM_RMAX for every q (256
+    // is a multiple of GM_RMAX), l = t / GM_RMAX + (256 / GM_RMAX) q; pairs
+    // outside the model are formed from in-range LDS columns and not written
     constexpr int PP = GM_RMAX * GM_RMAX / 256;
+    static_assert(256 % GM_RMAX == 0, "pairs of a thread share their first column");
+    const int jt = threadIdx.x % GM_RMAX, lt = threadIdx.x / GM_RMAX;
     double s[PP];
-    int jq[PP], lq[PP];   // the pairs; pairs outside the model read column 0 and are not written
 #pragma unroll
-    for (int q = 0; q < PP; ++q) {
-      s[q] = 0.0;
-      const int e = threadIdx.x + 256 * q;
-      const int j = e % GM_RMAX, l = e / GM_RMAX;
-      const bool ok = j < r && l < r && j <= l;
-      jq[q] = ok ? j : 0;
-      lq[q] = ok ? l : 0;
-    }
+    for (int q = 0; q < PP; ++q) s[q] = 0.0;
     for (int64_t i0 = 0; i0 < n; i0 += GM_ROWS) {
       gm_stage(A, I.lda, n, r, i0, nullptr, sA);
       __syncthreads();
       const int rows = (int)min((int64_t)GM_ROWS, n - i0);
       // every pair advances in the same row loop (independent chains, no
-      // per-thread branch), each summing over the rows in order
+      // per-thread branch), each summing over the rows in order; A[i][j]
+      // is read once for the thread's pairs
 #pragma unroll 4
-      for (int ii = 0; ii < rows; ++ii)
+      for (int ii = 0; ii < rows; ++ii) {
+        const double aj = sA[ii][jt];
 #pragma unroll
-        for (int q = 0; q < PP; ++q) s[q] = fma(sA[ii][jq[q]], sA[ii][lq[q]], s[q]);
+        for (int q = 0; q < PP; ++q) s[q] = fma(aj, sA[ii][lt + (256 / GM_RMAX) * q], s[q]);
+      }
       __syncthreads();
     }
 #pragma unroll
@@ -395,12 +395,26 @@ __global__ __launch_bounds__(256) void k_gmodel(const GInst<T>* insts, const GIt
       gm_stage(A, I.lda, n, r, i0, lam, sA);
       __syncthreads();
       const int rows = (int)min((int64_t)GM_ROWS, n - i0);
-      for (int e = threadIdx.x; e < rows * r; e += 256) {
-        const int ii = e % rows, j = e / rows;
-        double s = 0.0;
-#pragma unroll 4
-        for (int l = 0; l < r; ++l) s = fma(sA[ii][l], sC[j * r + l], s);
-        gstore(I.YM + ((int64_t)k * r + j) * n + i0 + ii, s);
+      // lane ii of wave w forms row ii for the columns j = w, w + 4, ...: one
+      // read of A[ii][l] serves GM_RMAX / 4 columns, and a wave's reads of C
+      // are broadcasts; every element sums over l in order
+      static_assert(GM_ROWS == 64 && GM_RMAX % 4 == 0, "one row per lane, four waves");
+      constexpr int JB = GM_RMAX / 4;
+      const int ii = threadIdx.x % GM_ROWS, jw = threadIdx.x / GM_ROWS;
+      if (ii < rows) {
+        double s[JB];
+#pragma unroll
+        for (int b = 0; b < JB; ++b) s[b] = 0.0;
+        for (int l = 0; l < r; ++l) {
+          const double a = sA[ii][l];
+#pragma unroll
+          for (int b = 0; b < JB; ++b) s[b] = fma(a, sC[(jw + 4 * b) * r + l], s[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+          const int j = jw + 4 * b;
+          if (j < r) gstore(I.YM + ((int64_t)k * r + j) * n + i0 + ii, s[b]);
+        }
       }
     }
   } else {

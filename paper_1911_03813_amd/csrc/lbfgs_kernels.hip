@@ -315,9 +315,15 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbParams
   if (threadIdx.x < LB_ND) {
     const int i = threadIdx.x;
     double v = 0.0;
-    for (int b = 0; b < ln.nb; ++b) {
-      const double pv = ln.part[(int64_t)b * LB_ND + i];
-      v = i == LB_MAXG ? fmax(v, pv) : v + pv;
+    // the chunk partials in order, eight loads in flight at a time (from
+    // valid chunks; those past nb are not used)
+    for (int b0 = 0; b0 < ln.nb; b0 += 8) {
+      double pv[8];
+#pragma unroll
+      for (int h = 0; h < 8; ++h) pv[h] = gload(ln.part + (int64_t)min(b0 + h, ln.nb - 1) * LB_ND + i);
+#pragma unroll
+      for (int h = 0; h < 8; ++h)
+        if (b0 + h < ln.nb) v = i == LB_MAXG ? fmax(v, pv[h]) : v + pv[h];
     }
     D[i] = v;
   }

@@ -49,6 +49,25 @@ def strip(rq):
     return {k: v for k, v in rq.items() if k != "host"}
 
 
+def max_overlap(results):
+    """Largest number of requests on the device at one time, from their
+    [t_admit, t_done] intervals."""
+    ev = sorted([(r["t_admit"], 1) for r in results] + [(r["t_done"], -1) for r in results],
+                key=lambda e: (e[0], e[1]))
+    cur = best = 0
+    for _, k in ev:
+        cur += k
+        best = max(best, cur)
+    return best
+
+
+def admitted_while_running(results):
+    """Pairs (a, b) where b was admitted after a and before a finished: b
+    joined a batch that was already on the device."""
+    return [(a["id"], b["id"]) for a in results for b in results
+            if a is not b and a["t_admit"] < b["t_admit"] < a["t_done"]]
+
+
 def drain(srv, count, timeout_s=120):
     got = {}
     t0 = time.time()
@@ -74,6 +93,13 @@ def test_served_results_equal_alone(ctx):
         assert st["completed"] == len(reqs) and st["queued"] == 0 and st["running"] == 0
     finally:
         srv.close()
+    # the requests really were in a mix: some ran together, and some joined
+    # while others were already running
+    res_all = [got[i] for i in ids]
+    joined = admitted_while_running(res_all)
+    print(f"max overlap {max_overlap(res_all)}, joined while running {joined}", flush=True)
+    assert max_overlap(res_all) >= 2
+    assert joined
     for rid, rq in zip(ids, reqs):
         res = got[rid]
         assert res["status"] == 0
@@ -113,8 +139,13 @@ def test_admission_by_memory(ctx):
             for res in srv.poll(64, timeout_ms=20):
                 got[res["id"]] = res
             assert time.time() - t0 < 120
-        print(f"peak running {seen_running}, per-request footprint ~{peak_one}", flush=True)
+        overlap = max_overlap([got[i] for i in ids])
+        print(f"peak running {seen_running} (stats) / {overlap} (intervals), per-request footprint ~{peak_one}",
+              flush=True)
         assert all(got[i]["status"] == 0 for i in ids)
+        # the budget holds about two requests: they ran two at a time, never all five
+        assert max(seen_running, overlap) >= 2
+        assert seen_running < len(ids)
         # a request larger than the whole budget is refused at submit
         big = requests([(256, 32, 3)], 52)[0]
         with pytest.raises(S.SymtdError) as e:

@@ -20,7 +20,14 @@
  *   - Errors found while checking arguments return a negative status and
  *     launch nothing; symtd_last_error() then describes the problem.  HIP
  *     errors are returned as SYMTD_EDEVICE with the HIP message attached.
- *   - A context is not thread-safe: use one per host thread.
+ *   - Errors found on the device during an asynchronous call (a split
+ *     product's bounded wait for a neighbouring block that gave up, which
+ *     leaves that call's results invalid) are recorded in the context and
+ *     returned as SYMTD_EDEVICE by the next call on the context made after
+ *     the device recorded them, or by symtd_check; the record is then
+ *     cleared, and later calls run normally.
+ *   - A context is not thread-safe and serves one stream at a time: use one
+ *     per host thread, and do not let calls on different streams overlap.
  */
 #ifndef SYMTD_H
 #define SYMTD_H
@@ -78,6 +85,11 @@ const char* symtd_last_error(const symtd_ctx* ctx);
 
 /* Static name of a status code. */
 const char* symtd_status_string(symtd_status s);
+
+/* Wait for `stream` and return SYMTD_EDEVICE if a call on this context
+ * recorded a device-side error (see the conventions above), clearing the
+ * record; SYMTD_OK otherwise. */
+symtd_status symtd_check(symtd_ctx* ctx, void* stream);
 
 /*
  * Objective and gradient, Algorithm 2 (fg_implicit) of the paper:
@@ -359,8 +371,8 @@ void symtd_server_result_release(symtd_server_result* res);
 void symtd_server_destroy(symtd_server* srv);
 
 /*
- * Work-split tuning of the evaluation kernels (used by the autotuner and by
- * tests that force particular splits). Keys:
+ * Work-split tuning of the evaluation kernels (tests force particular splits
+ * with it). Keys:
  *   SYMTD_TUNE_G1_BLOCKS  blocks sharing the first product V'A (0 = automatic:
  *                         one per compute unit, never more than the number of
  *                         observation slabs; larger requests are clamped)
@@ -369,10 +381,19 @@ void symtd_server_destroy(symtd_server* srv);
  *   SYMTD_TUNE_GRAPH      grouped engine (batched solve, server): 1 (default)
  *                         = capture one evaluation step as a hipGraph and
  *                         replay it; 0 = launch the step's kernels eagerly
- * Values must be >= 0; results do not depend on them beyond rounding order.
+ *   SYMTD_TUNE_SPIN_LIMIT polls after which the first product's wait for a
+ *                         neighbouring block's partial gives up (0 =
+ *                         automatic, 2^24); a give-up is reported as above
+ *   SYMTD_TUNE_FAULT_HANDOFF  testing: 1 = the first product's waits watch
+ *                         for a flag value that no block writes, so each
+ *                         runs out its spin limit and gives up (every kernel
+ *                         still exits); 0 (default) = off
+ * Values must be >= 0; results do not depend on the split keys beyond
+ * rounding order.
  */
 typedef enum symtd_tune_key {
-  SYMTD_TUNE_G1_BLOCKS = 0, SYMTD_TUNE_G2_SPLITS = 1, SYMTD_TUNE_GRAPH = 3   /* 2: unused */
+  SYMTD_TUNE_G1_BLOCKS = 0, SYMTD_TUNE_G2_SPLITS = 1, SYMTD_TUNE_GRAPH = 3,   /* 2: unused */
+  SYMTD_TUNE_SPIN_LIMIT = 4, SYMTD_TUNE_FAULT_HANDOFF = 5
 } symtd_tune_key;
 symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value);
 

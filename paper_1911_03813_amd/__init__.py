@@ -111,6 +111,7 @@ SIGNATURES = {
     "symtd_destroy": (None, [_vp]),
     "symtd_last_error": (_c.c_char_p, [_vp]),
     "symtd_status_string": (_c.c_char_p, [_int]),
+    "symtd_check": (_int, [_vp, _vp]),
     "symtd_fg": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int,
                         _dbl, _int, _vp, _vp, _vp, _i64]),
     "symtd_fg_multi": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _int,
@@ -265,6 +266,7 @@ def symtd_fg(ctx: Context, V, nu, A, lam, d: int, alpha: float = 0.0, prec: int 
                         float(alpha), int(prec), _vec(f, "f", 1), _vec(g, "g_lambda", r), Gp, ldg)
     _check(ctx, st)
     return f, g, G
+
 
 
 def symtd_fg_multi(ctx: Context, V, nu, A, lam, r: int, d: int, alpha: float = 0.0, prec: int | None = None,
@@ -559,7 +561,13 @@ def symtd_normX(ctx: Context, V, nu, d: int, out=None, stream=None):
     return a
 
 
-TUNE_G1_BLOCKS, TUNE_G2_SPLITS, TUNE_GRAPH = 0, 1, 3
+TUNE_G1_BLOCKS, TUNE_G2_SPLITS, TUNE_GRAPH, TUNE_SPIN_LIMIT, TUNE_FAULT_HANDOFF = 0, 1, 3, 4, 5
+
+
+def symtd_check(ctx: Context, stream=None):
+    """Wait for the stream; raise SymtdError (EDEVICE) if a call on this
+    context recorded a device-side error (the record is then cleared)."""
+    _check(ctx, lib().symtd_check(ctx.handle, _stream(stream)))
 
 
 def symtd_set_tuning(ctx: Context, key: int, value: int):

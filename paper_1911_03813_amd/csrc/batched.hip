@@ -136,6 +136,7 @@ symtd_status symtd_fg_batched(symtd_ctx* ctx, void* stream, symtd_dtype dt, symt
                               const symtd_fg_item* items) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
+  if (symtd_status s0 = ctx->take_device_error(); s0 != SYMTD_OK) return s0;
   if (count < 0 || (count > 0 && !items)) return ctx->fail(SYMTD_EINVAL, "bad item list");
   if (!((dt == SYMTD_F64 && prec == SYMTD_PREC_FP64) || (dt == SYMTD_F32 && prec == SYMTD_PREC_FP32)))
     return ctx->fail(SYMTD_EINVAL, "unsupported storage/precision pair (dt=%d, prec=%d)", (int)dt, (int)prec);
@@ -165,6 +166,7 @@ symtd_status symtd_solve_batched(symtd_ctx* ctx, void* stream, int64_t count, co
                                  const symtd_solve_opts* opts, symtd_solve_result* outs) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
+  if (symtd_status s0 = ctx->take_device_error(); s0 != SYMTD_OK) return s0;
   if (count < 0 || (count > 0 && (!pbs || !opts || !outs))) return ctx->fail(SYMTD_EINVAL, "bad problem list");
   for (int64_t i = 0; i < count; ++i) {
     symtd_status s = check_solve(ctx, &pbs[i], &opts[i], &outs[i]);

@@ -83,7 +83,7 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
   for (int t0 = 0; t0 < nt_tot; t0 += LP_NT_MAX) {
     const int nt = std::min(LP_NT_MAX, nt_tot - t0);
     LpG1Args a1{D->Vc, D->ldc, D->kc_len, D->plane_c, D->nu, (int)n, (int)p, Ac, aplane, 16 * t0, rp, nslab1,
-                nblocks1, d, D->wscale, W, D->kr_len, wplane, wpart, part, ctx->flags, ctx->dev_err};
+                nblocks1, d, D->wscale, W, D->kr_len, wplane, wpart, part, ctx->handoff()};
     ctx->prof_begin(0, st);
     launch_lp_gemm1(kind, nt, dim3(nblocks1), st, a1);
     ctx->prof_end(0, st);
@@ -190,6 +190,7 @@ symtd_status symtd_fg_data(symtd_ctx* ctx, void* stream, const symtd_data* D, co
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
   if (!D) return ctx->fail(SYMTD_EINVAL, "null data handle");
+  if (symtd_status s0 = ctx->take_device_error(); s0 != SYMTD_OK) return s0;
   if (D->kind < 0) {
     return symtd_fg(ctx, stream, D->dt, D->V, D->ldv, D->nu, D->n, D->p, A, lda, lambda, r, d, alpha, D->prec, f,
                     g_lambda, G_A, ldg);

@@ -336,10 +336,9 @@ class GroupEngine {
     lane_done_host_.resize(nlanes_);
     if ((e = hipMemcpyAsync(lane_done_host_.data(), d_lane_done_, sizeof(int) * nlanes_, hipMemcpyDeviceToHost, st_)) !=
             hipSuccess ||
-        (e = hipMemcpyAsync(host_, ctx_->dev_err, sizeof(int), hipMemcpyDeviceToHost, st_)) != hipSuccess ||
         (e = hipStreamSynchronize(st_)) != hipSuccess)
       return ctx_->hip_fail(e, "engine poll");
-    if (host_[0]) return ctx_->fail(SYMTD_EDEVICE, "a device wait gave up");
+    if (symtd_status s = ctx_->take_device_error(); s != SYMTD_OK) return s;
     int L = 0;
     for (auto* I : live_) {
       bool all = true;

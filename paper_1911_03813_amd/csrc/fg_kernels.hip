@@ -57,12 +57,16 @@ namespace symtd {
 // within one chunk.  There are never more blocks than slabs, so a slab is
 // shared by at most two blocks: the block holding its first chunks owns it;
 // the block holding its last chunks (at the start of its range) publishes
-// that partial accumulator through `part` and raises its `flag`; the owner,
-// which reaches the slab at the end of its own range, adds the partial,
-// lowers the flag again and runs the epilogue.  A block waits only after its
-// own work, and only for its successor, which publishes before it waits for
-// anything, so the wait always ends even when not every block is resident;
-// a spin limit guards it regardless.
+// that partial accumulator through `part` and raises its flag to the
+// launch's epoch; the owner, which reaches the slab at the end of its own
+// range, waits for that value, adds the partial and runs the epilogue.  A
+// block waits only after its own work, and only for its successor, which
+// publishes before it waits for anything, so the wait ends once the
+// successor has run.  There are never more blocks than compute units and a
+// block fits one, so on a device the launch has to itself all blocks are
+// resident together; work on another stream holding compute units could
+// delay a successor, so a spin limit bounds the wait and a give-up is
+// reported through the context's error word (Handoff).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct G1Shape {
@@ -326,11 +330,11 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
           }
         xput_complete();   // each wave's stores are done (visible device-wide)
         __syncthreads();   // ... before the flag is raised
-        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.ho.flag + blk, a.ho.put, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         if (ke < KC) {
           // the next block holds chunks [ke, KC) of this slab
-          xwait_flag(a.flag + blk + 1, a.err);
+          xwait_flag(a.ho.flag + blk + 1, a.ho.want, a.ho.err, a.ho.spin_limit);
           const T* pp = a.part + opaque_uniform(blk + 1) * PART + (int64_t)wave * (MT * NT * 4 * 64);
 #pragma unroll
           for (int m = 0; m < MT; ++m)
@@ -341,8 +345,6 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) acc[m][t][v] += q4.e[v];
             }
-          __syncthreads();   // every wave has read the partial before the flag is lowered
-          if (tid == 0) __hip_atomic_store(a.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // epilogue: acc[m][t][v] = z at l = 16 b + row(g, v), j = col0 + 16t + c.
         // w = nu z^(d-1) in the storage precision, the power taken over all

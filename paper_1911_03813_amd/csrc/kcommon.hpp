@@ -176,20 +176,27 @@ __device__ __forceinline__ int64_t opaque_uniform(int64_t x) {
   return x;
 }
 
-// Spin until a hand-off flag is raised (relaxed device-scope loads), giving
-// up after a bounded number of polls: then *err is set and the caller goes
-// on with whatever the partial holds, so that every wave still exits.
-__device__ __forceinline__ void xwait_flag(const int* flag, int* err) {
+// Spin until a hand-off flag holds `want` (relaxed device-scope loads),
+// giving up after `limit` polls that did not see it: then *err (a word of
+// pinned host memory that the host checks at its next call) is set and the
+// caller goes on with whatever the partial holds, so that every wave still
+// exits.  Flags carry the launch's epoch rather than 1/0, so a value left by
+// an earlier launch (for instance after a give-up) never satisfies a later
+// wait and no flag needs to be lowered.  Returns whether the flag was seen.
+__device__ __forceinline__ bool xwait_flag(const int* flag, int want, int* err, int limit) {
   int spins = 0;
-  while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
-    __builtin_amdgcn_s_sleep(2);
-    if (++spins > (1 << 24)) {
-      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  bool ok = true;
+  while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != want) {
+    if (++spins > limit) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      ok = false;
       break;
     }
+    __builtin_amdgcn_s_sleep(2);
   }
   // keeps the compiler from moving the partial's reads above the wait
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  return ok;
 }
 
 // x^k for a small non-negative integer k (k is uniform across the wave).

@@ -45,6 +45,17 @@ template <typename T> constexpr int g1_waves() { return sizeof(T) == 8 ? 8 : G1_
 constexpr int G2_STAGES_F32 = 3;
 constexpr int G2_STAGES_F64 = 2;
 
+// Stream-K hand-off of a split product: flag[b] is raised to `put` by block
+// b once its partial is published; block b-1 waits for it to read `want`
+// (normally put: the launch's epoch, unique per launch and never 0) for at
+// most `spin_limit` polls, after which it sets *err (pinned host memory).
+struct Handoff {
+  int* flag;       // [blocks] hand-off flags
+  int* err;        // device address of the context's error word
+  int put, want;
+  int spin_limit;
+};
+
 template <typename T>
 struct G1Args {
   const T* V; int64_t ldv; const double* nu; int n; int p;
@@ -60,8 +71,7 @@ struct G1Args {
   T* Wp;         // packed W
   double* wpart; // [g1_waves<T>() * nblocks][rp] fp64 column partials, one row per wave
   T* part;       // [nblocks][g1_waves<T>() * g1_mt<T>() * NT * 256] published partial accumulators
-  int* flag;     // [nblocks] hand-off flags, zero between launches
-  int* err;      // set to 1 if a hand-off wait gave up
+  Handoff ho;    // stream-K hand-off between neighbouring blocks
 };
 
 template <typename T>

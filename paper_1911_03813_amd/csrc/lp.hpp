@@ -71,7 +71,7 @@ struct LpG1Args {
   double wscale;                                 // 2^s (fp16) or 1
   void* W; int64_t kr_len; int64_t wplane;       // W rows: kr_len observations
   double* wpart;                                 // [4 nblocks][rp]
-  float* part; int* flag; int* err;              // stream-K hand-off
+  float* part; Handoff ho;                       // stream-K hand-off
 };
 
 struct LpG2Args {

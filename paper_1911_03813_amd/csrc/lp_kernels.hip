@@ -272,18 +272,16 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
             xput4(pp + ((m * NT + t) * 64 + lane) * 4, acc[m][t]);
         xput_complete();   // each wave's stores are done (visible device-wide)
         __syncthreads();   // ... before the flag is raised
-        if (tid == 0) __hip_atomic_store(a.flag + blk, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.ho.flag + blk, a.ho.put, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         // owner (nl holds the slab's weights, loaded when the slab began)
         if (ke < KC) {
-          xwait_flag(a.flag + blk + 1, a.err);
+          xwait_flag(a.ho.flag + blk + 1, a.ho.want, a.ho.err, a.ho.spin_limit);
           const float* pp = a.part + (blk + 1) * PART + (int64_t)wave * (LP_MT * NT * 256);
   #pragma unroll
           for (int m = 0; m < LP_MT; ++m)
   #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] += xget4v(pp + ((m * NT + t) * 64 + lane) * 4);
-          __syncthreads();
-          if (tid == 0) __hip_atomic_store(a.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // epilogue: acc[m][t][v] = z at l = lb + v, column col0 + 16 t + c.
         // w = nu z^(d-1) in fp32 (its 16-bit storage rounds far more); the

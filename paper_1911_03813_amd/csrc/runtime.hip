@@ -100,6 +100,25 @@ void symtd_ctx::prof_end(int which, hipStream_t st) {
   (void)hipEventRecord(pending.back().stop, st);
 }
 
+symtd::Handoff symtd_ctx::handoff() {
+  if (++epoch > 0x3fffffffu) epoch = 1;   // never 0 (the flags' initial value)
+  symtd::Handoff h;
+  h.flag = flags;
+  h.err = err_dev;
+  h.put = (int)epoch;
+  h.want = tune_fault ? (int)(epoch | 0x40000000u) : (int)epoch;   // the former is never written
+  h.spin_limit = tune_spin > 0 ? (int)std::min<int64_t>(tune_spin, 0x7fffffff) : (1 << 24);
+  return h;
+}
+
+symtd_status symtd_ctx::take_device_error() {
+  if (!err_host || __atomic_load_n(err_host, __ATOMIC_ACQUIRE) == 0) return SYMTD_OK;
+  __atomic_store_n(err_host, 0, __ATOMIC_RELEASE);
+  return fail(SYMTD_EDEVICE,
+              "a split product's hand-off wait gave up in an earlier call on this context; the results of that "
+              "call are invalid");
+}
+
 symtd_status symtd_ctx::set_device() {
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -186,16 +205,28 @@ namespace symtd {
 template <typename T>
 symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu,
                     int64_t n, int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int ng,
-                    int d, double alpha, double* f, double* g_lambda, T* G, int64_t ldg) {
+                    int d, double alpha, double* f, double* g_lambda, T* G, int64_t ldg,
+                    void* fixed_ws, size_t fixed_bytes) {
   const bool f64 = sizeof(T) == 8;
   const int64_t r1 = r;            // columns of one model
   r = r1 * ng;                     // columns of all models (the products see them all)
   FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count, ctx->tune_g1_blocks, ctx->tune_g2_splits);
   P.rr = (size_t)ng * r1 * r1;      // B and C: one r1 x r1 block per model
   if (P.nblocks > ctx->nflags) return ctx->fail(SYMTD_EINVAL, "internal: %d blocks exceed the flag array", P.nblocks);
-  symtd_status s = ctx->reserve(P.bytes(sizeof(T)));
-  if (s != SYMTD_OK) return s;
-  Carve cv(ctx->ws);
+  const size_t need = P.bytes(sizeof(T));
+  void* base = fixed_ws;
+  const uint32_t prof_mask = ctx->prof_mask;
+  if (fixed_ws) {
+    if (need > fixed_bytes)
+      return ctx->fail(SYMTD_EINVAL, "the evaluation needs %zu bytes of workspace, more than the %zu of the fixed "
+                       "scratch array", need, fixed_bytes);
+    ctx->prof_mask = 0;
+  } else {
+    symtd_status s = ctx->reserve(need);
+    if (s != SYMTD_OK) return s;
+    base = ctx->ws;
+  }
+  Carve cv(base);
   T* Apad = cv.take<T>(P.apad);
   T* Wp = cv.take<T>(P.wp);
   double* wpart = cv.take<double>(P.wpart);
@@ -228,7 +259,7 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   for (int t0 = 0; t0 < P.nt_tot; t0 += P.nt1) {
     const int nt = std::min(P.nt1, P.nt_tot - t0);
     G1Args<T> a1{V, ldv, nu, (int)n, (int)p, A, lda, (int)r, 16 * t0, P.nt_tot, P.rp, P.nblk,
-                 P.nslab, P.nblocks, d, Apad, P.ldap, Wp, wpart, part, ctx->flags, ctx->dev_err};
+                 P.nslab, P.nblocks, d, Apad, P.ldap, Wp, wpart, part, ctx->handoff()};
     ctx->prof_begin(0, st);
     launch_gemm1(nt, dma, dim3(P.nblocks), st, a1);
     ctx->prof_end(0, st);
@@ -254,6 +285,7 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
     launch_final(st, fa);
   }
   ctx->prof_end(3, st);
+  ctx->prof_mask = prof_mask;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ctx->hip_fail(e, "kernel launch (fg)");
   return SYMTD_OK;
@@ -261,10 +293,10 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
 
 template symtd_status run_fg<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t,
                                     int64_t, const float*, int64_t, const double*, int64_t, int, int, double,
-                                    double*, double*, float*, int64_t);
+                                    double*, double*, float*, int64_t, void*, size_t);
 template symtd_status run_fg<double>(symtd_ctx*, hipStream_t, const double*, int64_t, const double*, int64_t,
                                      int64_t, const double*, int64_t, const double*, int64_t, int, int, double,
-                                     double*, double*, double*, int64_t);
+                                     double*, double*, double*, int64_t, void*, size_t);
 
 template <typename T>
 symtd_status run_rrf(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, int64_t n, int64_t p, int64_t r,
@@ -491,17 +523,21 @@ symtd_status symtd_create(int device, symtd_ctx** out) {
   if (!c) return SYMTD_ENOMEM;
   c->device = device;
   c->cu_count = prop.multiProcessorCount;
-  // flags, the error word and the arrival counters in one zeroed allocation
-  const size_t words = 4 * (size_t)c->cu_count + 1 + symtd_ctx::kFinalCounters;
+  // flags and the arrival counters in one zeroed allocation; the error word
+  // in pinned, device-mapped host memory
+  const size_t words = 4 * (size_t)c->cu_count + symtd_ctx::kFinalCounters;
   if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->flags, sizeof(int) * words) != hipSuccess ||
-      hipMemset(c->flags, 0, sizeof(int) * words) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      hipMemset(c->flags, 0, sizeof(int) * words) != hipSuccess ||
+      hipHostMalloc((void**)&c->err_host, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->err_dev, c->err_host, 0) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     symtd_destroy(c);
     return SYMTD_EDEVICE;
   }
+  *c->err_host = 0;
   c->nflags = 4 * c->cu_count;  // >= the blocks of any split product
-  c->dev_err = c->flags + c->nflags;
-  c->final_count = c->dev_err + 1;
+  c->final_count = c->flags + c->nflags;
   *out = c;
   return SYMTD_OK;
 }
@@ -517,6 +553,7 @@ void symtd_destroy(symtd_ctx* ctx) {
   if (ctx->sws) (void)hipFree(ctx->sws);
   if (ctx->wide) (void)hipFree(ctx->wide);
   if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
+  if (ctx->err_host) (void)hipHostFree(ctx->err_host);
   delete ctx;
 }
 
@@ -533,14 +570,16 @@ symtd_status symtd_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* 
                         G_A, ldg);
 }
 
-symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
-                            const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
-                            const double* lambda, int64_t r, int64_t models, int d, double alpha, symtd_prec prec,
-                            double* f, double* g_lambda, void* G_A, int64_t ldg) {
+static symtd_status fg_multi_impl(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
+                                  const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
+                                  const double* lambda, int64_t r, int64_t models, int d, double alpha,
+                                  symtd_prec prec, double* f, double* g_lambda, void* G_A, int64_t ldg,
+                                  void* fixed_ws, size_t fixed_bytes) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
-  symtd_status s = ctx->check_common(dt, V, ldv, nu, n, p, d);
+  symtd_status s = ctx->take_device_error();
   if (s != SYMTD_OK) return s;
+  if ((s = ctx->check_common(dt, V, ldv, nu, n, p, d)) != SYMTD_OK) return s;
   if (r < 1 || models < 1 || r * models > 0x7fffffffLL)
     return ctx->fail(SYMTD_EINVAL, "rank r=%lld and models=%lld must be >= 1", (long long)r, (long long)models);
   if (lda < n || ldg < n) return ctx->fail(SYMTD_EINVAL, "lda=%lld and ldg=%lld must be >= n=%lld",
@@ -556,17 +595,27 @@ symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt, const 
   hipStream_t st = (hipStream_t)stream;
   if (dt == SYMTD_F64)
     return run_fg<double>(ctx, st, (const double*)V, ldv, nu, n, p, (const double*)A, lda, lambda, r, (int)models, d,
-                          alpha, f, g_lambda, (double*)G_A, ldg);
+                          alpha, f, g_lambda, (double*)G_A, ldg, fixed_ws, fixed_bytes);
   return run_fg<float>(ctx, st, (const float*)V, ldv, nu, n, p, (const float*)A, lda, lambda, r, (int)models, d,
-                       alpha, f, g_lambda, (float*)G_A, ldg);
+                       alpha, f, g_lambda, (float*)G_A, ldg, fixed_ws, fixed_bytes);
 }
+
+symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
+                            const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
+                            const double* lambda, int64_t r, int64_t models, int d, double alpha, symtd_prec prec,
+                            double* f, double* g_lambda, void* G_A, int64_t ldg) {
+  return fg_multi_impl(ctx, stream, dt, V, ldv, nu, n, p, A, lda, lambda, r, models, d, alpha, prec, f, g_lambda,
+                       G_A, ldg, nullptr, 0);
+}
+
 
 symtd_status symtd_normX(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
                          const double* nu, int64_t n, int64_t p, int d, double* alpha) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
-  symtd_status s = ctx->check_common(dt, V, ldv, nu, n, p, d);
+  symtd_status s = ctx->take_device_error();
   if (s != SYMTD_OK) return s;
+  if ((s = ctx->check_common(dt, V, ldv, nu, n, p, d)) != SYMTD_OK) return s;
   if (!alpha) return ctx->fail(SYMTD_EINVAL, "null alpha");
   if (!aligned_to<char>(alpha, 8)) return ctx->fail(SYMTD_EALIGN, "alpha misaligned");
   if ((s = ctx->set_device()) != SYMTD_OK) return s;
@@ -582,8 +631,20 @@ symtd_status symtd_set_tuning(symtd_ctx* ctx, symtd_tune_key key, int64_t value)
     case SYMTD_TUNE_G1_BLOCKS: ctx->tune_g1_blocks = value; return SYMTD_OK;
     case SYMTD_TUNE_G2_SPLITS: ctx->tune_g2_splits = value; return SYMTD_OK;
     case SYMTD_TUNE_GRAPH: ctx->tune_graph = value; return SYMTD_OK;
+    case SYMTD_TUNE_SPIN_LIMIT: ctx->tune_spin = value; return SYMTD_OK;
+    case SYMTD_TUNE_FAULT_HANDOFF: ctx->tune_fault = value; return SYMTD_OK;
   }
   return ctx->fail(SYMTD_EINVAL, "unknown tuning key %d", (int)key);
+}
+
+symtd_status symtd_check(symtd_ctx* ctx, void* stream) {
+  if (!ctx) return SYMTD_EINVAL;
+  ctx->err.clear();
+  symtd_status s = ctx->set_device();
+  if (s != SYMTD_OK) return s;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamSynchronize");
+  return ctx->take_device_error();
 }
 
 symtd_status symtd_profile_enable(symtd_ctx* ctx, uint32_t mask) {

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "kernels.hpp"
 #include "symtd.h"
 
 struct symtd_ctx {
@@ -20,17 +21,23 @@ struct symtd_ctx {
   size_t wide_bytes = 0;
   int* host_flag = nullptr;   // pinned host word for polling the solver's stop count
   double fwide_host = 0.0;    // host landing of the final fp64 evaluation
-  // hand-off flags of the split products (zero between launches), a device
-  // error word set if a hand-off wait ever gives up, and the arrival
-  // counters of the closing step, one per model (zero between launches)
+  // hand-off flags of the split products (tagged with a launch epoch), and
+  // the arrival counters of the closing step, one per model (zero between
+  // launches)
   int* flags = nullptr;
   int nflags = 0;
-  int* dev_err = nullptr;
   int* final_count = nullptr;
   static constexpr int kFinalCounters = 1024;
+  uint32_t epoch = 0;        // of the last split-product launch
+  // error word in pinned host memory: a kernel whose hand-off wait gave up
+  // sets it (err_dev is its device address); every call checks it first
+  int* err_host = nullptr;
+  int* err_dev = nullptr;
   // work-split overrides (0 = automatic)
   int64_t tune_g1_blocks = 0, tune_g2_splits = 0;
   int64_t tune_graph = 1;   // grouped engine: replay captured steps (1) or launch eagerly (0)
+  int64_t tune_spin = 0;    // polls before a hand-off wait gives up (0 = automatic)
+  int64_t tune_fault = 0;   // testing: hand-off waits watch for a value no block writes
 
   // per-kernel timing (symtd_profile_*): kernels whose bit is set in
   // prof_mask are bracketed by events taken from a reusable pool
@@ -46,6 +53,10 @@ struct symtd_ctx {
   symtd_status set_device();
   symtd_status check_common(symtd_dtype dt, const void* V, int64_t ldv, const double* nu,
                             int64_t n, int64_t p, int d);
+  // hand-off arguments of the next split-product launch (a fresh epoch)
+  symtd::Handoff handoff();
+  // SYMTD_EDEVICE (and the word cleared) if a kernel set the error word
+  symtd_status take_device_error();
   void prof_begin(int which, hipStream_t st);
   void prof_end(int which, hipStream_t st);
   hipEvent_t pool_event();
@@ -56,10 +67,14 @@ namespace symtd {
 // Algorithm 2 for `ng` models of r columns side by side (model m = columns
 // m r .. m r + r - 1 of A, lambda, g_lambda, G_A; f holds ng values).
 // Arguments are checked by the caller.
+// With `fixed_ws` the workspace is carved from those fixed_bytes instead of
+// the context's arena (SYMTD_EINVAL if it does not fit): nothing is
+// allocated, and no kernel is timed (timing would create events).
 template <typename T>
 symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu,
                     int64_t n, int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int ng,
-                    int d, double alpha, double* f, double* g_lambda, T* G, int64_t ldg);
+                    int d, double alpha, double* f, double* g_lambda, T* G, int64_t ldg,
+                    void* fixed_ws = nullptr, size_t fixed_bytes = 0);
 
 // Randomized range finder starts of `restarts` lanes (restart k = columns
 // k r .. k r + r - 1 of V Omega), normalised, written into each lane's x and

@@ -194,10 +194,9 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
     }
     if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "solver kernels");
     if ((e = hipMemcpyAsync(ctx->host_flag, Lay.done, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(ctx->host_flag + 1, ctx->dev_err, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return ctx->hip_fail(e, "polling the solver");
-    if (ctx->host_flag[1] != 0) return ctx->fail(SYMTD_EDEVICE, "a split-product hand-off wait gave up");
+    if ((s = ctx->take_device_error()) != SYMTD_OK) return s;
     if (ctx->host_flag[0] >= R) break;
     if (steps > step_cap) return ctx->fail(SYMTD_EDEVICE, "solver did not stop within %lld steps", (long long)steps);
   }
@@ -266,8 +265,9 @@ symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb, 
                          symtd_solve_result* out) {
   if (!ctx) return SYMTD_EINVAL;
   ctx->err.clear();
-  symtd_status s = check_solve(ctx, pb, o, out);
+  symtd_status s = ctx->take_device_error();
   if (s != SYMTD_OK) return s;
+  if ((s = check_solve(ctx, pb, o, out)) != SYMTD_OK) return s;
   if ((s = ctx->set_device()) != SYMTD_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if (pb->dt == SYMTD_F64) return run_solve<double>(ctx, st, *pb, *o, out);

@@ -32,6 +32,7 @@
 #ifndef SYMTD_H
 #define SYMTD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -118,6 +119,28 @@ symtd_status symtd_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt,
                       const void* A, int64_t lda, const double* lambda, int64_t r, int d,
                       double alpha, symtd_prec prec,
                       double* f, double* g_lambda, void* G_A, int64_t ldg);
+
+/*
+ * symtd_fg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * arguments, results and kernels are those of symtd_fg (the results are the
+ * same bits), but the call allocates nothing: its workspace is a fixed
+ * array of SYMTD_NOALLOC_SCRATCH_BYTES in device memory, one per GPU that
+ * the library runs on, held until the process ends (its address is looked
+ * up by symtd_create).  Returns SYMTD_EINVAL if the evaluation's workspace
+ * does not fit (it grows with p r + p_splits n r; d = 4, n = 100, p = 5000,
+ * r = 20 in fp64 needs about 16 MB, the n = 1000, p = 1e5, r = 100 fp32
+ * evaluation 81 MB and does not fit).  Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU, from any context or stream,
+ * race; calls in stream order are safe (nothing in the array needs to start
+ * at zero).  Per-kernel timing (symtd_profile_*) does not apply to it.
+ */
+#define SYMTD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+symtd_status symtd_fg_noalloc(symtd_ctx* ctx, void* stream, symtd_dtype dt,
+                              const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
+                              const void* A, int64_t lda, const double* lambda, int64_t r, int d,
+                              double alpha, symtd_prec prec,
+                              double* f, double* g_lambda, void* G_A, int64_t ldg);
 
 /*
  * Data handles: a data set (V, nu) prepared once for repeated evaluations.

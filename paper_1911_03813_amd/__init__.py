@@ -20,6 +20,7 @@ PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG_DIR, "libsymtd.so")
 
 SYMTD_OK = 0
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SYMTD_NOALLOC_SCRATCH_BYTES of include/symtd.h
 STATUS = {0: "SYMTD_OK", -1: "SYMTD_EINVAL", -2: "SYMTD_EALIGN", -3: "SYMTD_ENOMEM",
           -4: "SYMTD_EDEVICE", -5: "SYMTD_EUNSUPPORTED", -6: "SYMTD_ENONFINITE", -7: "SYMTD_EREJECTED"}
 F64, F32 = 0, 1
@@ -114,6 +115,8 @@ SIGNATURES = {
     "symtd_check": (_int, [_vp, _vp]),
     "symtd_fg": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int,
                         _dbl, _int, _vp, _vp, _vp, _i64]),
+    "symtd_fg_noalloc": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int,
+                                _dbl, _int, _vp, _vp, _vp, _i64]),
     "symtd_fg_multi": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _int,
                               _dbl, _int, _vp, _vp, _vp, _i64]),
     "symtd_normX": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _vp]),
@@ -238,7 +241,7 @@ def _stream(stream):
 # --- entry points -------------------------------------------------------------
 
 def symtd_fg(ctx: Context, V, nu, A, lam, d: int, alpha: float = 0.0, prec: int | None = None,
-             out=None, stream=None):
+             out=None, stream=None, noalloc: bool = False):
     """f, g_lambda, G_A of Algorithm 2 for (nu, V) and the model (lam, A).
 
     Returns device tensors (f: shape (1,) float64, g_lambda: (r,) float64,
@@ -262,11 +265,19 @@ def symtd_fg(ctx: Context, V, nu, A, lam, d: int, alpha: float = 0.0, prec: int 
     else:
         f, g, G = out
     Gp, ldg = _mat(G, "G_A", V.dtype)
-    st = lib().symtd_fg(ctx.handle, _stream(stream), _dt(V), Vp, ldv, nup, n, p, Ap, lda, lp, r, int(d),
-                        float(alpha), int(prec), _vec(f, "f", 1), _vec(g, "g_lambda", r), Gp, ldg)
+    entry = lib().symtd_fg_noalloc if noalloc else lib().symtd_fg
+    st = entry(ctx.handle, _stream(stream), _dt(V), Vp, ldv, nup, n, p, Ap, lda, lp, r, int(d),
+               float(alpha), int(prec), _vec(f, "f", 1), _vec(g, "g_lambda", r), Gp, ldg)
     _check(ctx, st)
     return f, g, G
 
+
+def symtd_fg_noalloc(ctx: Context, V, nu, A, lam, d: int, alpha: float = 0.0, prec: int | None = None,
+                     out=None, stream=None):
+    """symtd_fg through the entry point that allocates no device memory (its
+    workspace is the library's fixed per-device scratch array).  With `out`
+    given, nothing is allocated on the Python side either."""
+    return symtd_fg(ctx, V, nu, A, lam, d, alpha, prec, out, stream, noalloc=True)
 
 
 def symtd_fg_multi(ctx: Context, V, nu, A, lam, r: int, d: int, alpha: float = 0.0, prec: int | None = None,

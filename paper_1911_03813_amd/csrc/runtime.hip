@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -472,6 +473,36 @@ template symtd_status run_normx<double>(symtd_ctx*, hipStream_t, const double*, 
 }  // namespace symtd
 
 // ---------------------------------------------------------------------------
+// the fixed scratch array of symtd_fg_noalloc: one copy per device, alive
+// until the process ends.  In host code `scratch` only stands in for the
+// symbol; its device address (per device) comes from hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+static constexpr size_t kNoallocBytes = SYMTD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;   // device address of `scratch`, per device id
+
+// with `device` current: its address of the scratch array (looked up once)
+symtd_status scratch_address(symtd_ctx* c, int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize((size_t)device + 1, nullptr);
+  if (!g_scratch_addr[(size_t)device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return SYMTD_EDEVICE;
+    }
+    g_scratch_addr[(size_t)device] = ptr;
+  }
+  c->noalloc_ws = g_scratch_addr[(size_t)device];
+  return SYMTD_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // argument checks shared by the entry points
 // ---------------------------------------------------------------------------
 symtd_status symtd_ctx::check_common(symtd_dtype dt, const void* V, int64_t ldv, const double* nu,
@@ -538,6 +569,10 @@ symtd_status symtd_create(int device, symtd_ctx** out) {
   *c->err_host = 0;
   c->nflags = 4 * c->cu_count;  // >= the blocks of any split product
   c->final_count = c->flags + c->nflags;
+  if (scratch_address(c, device) != SYMTD_OK) {
+    symtd_destroy(c);
+    return SYMTD_EDEVICE;
+  }
   *out = c;
   return SYMTD_OK;
 }
@@ -608,6 +643,15 @@ symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt, const 
                        G_A, ldg, nullptr, 0);
 }
 
+symtd_status symtd_fg_noalloc(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
+                              const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
+                              const double* lambda, int64_t r, int d, double alpha, symtd_prec prec,
+                              double* f, double* g_lambda, void* G_A, int64_t ldg) {
+  if (!ctx) return SYMTD_EINVAL;
+  if (!ctx->noalloc_ws) return ctx->fail(SYMTD_EDEVICE, "the fixed scratch array has no device address");
+  return fg_multi_impl(ctx, stream, dt, V, ldv, nu, n, p, A, lda, lambda, r, 1, d, alpha, prec, f, g_lambda, G_A,
+                       ldg, ctx->noalloc_ws, kNoallocBytes);
+}
 
 symtd_status symtd_normX(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
                          const double* nu, int64_t n, int64_t p, int d, double* alpha) {

@@ -19,6 +19,7 @@ struct symtd_ctx {
   size_t sws_bytes = 0;
   void* wide = nullptr; // device scratch of the final fp64 evaluation, grown on demand
   size_t wide_bytes = 0;
+  void* noalloc_ws = nullptr;   // this device's fixed scratch array (symtd_fg_noalloc)
   int* host_flag = nullptr;   // pinned host word for polling the solver's stop count
   double fwide_host = 0.0;    // host landing of the final fp64 evaluation
   // hand-off flags of the split products (tagged with a launch epoch), and

@@ -1,27 +1,36 @@
 """Benchmark of the objective-and-gradient evaluation (Algorithm 2), with the
-batched and served solve forms beside it.
+small and mid-size workloads, the batched and served solve forms beside it.
 
 Headline: one step = one symtd_fg call, f, g_lambda and G_A for the large
 single instance d=3, n=1000, r=100, p=100000 (Gaussian-mixture observations,
-sigma=1e-2, nu=1/p), fp32 storage and fp32 matrix-core products with fp64
-reductions and assembly.  Inputs are resident in device memory before the
-timed region starts.  The JSON line carries the throughput (evals/s), the
-roofline figures of the dominant kernel (timed with HIP events on its launch
-stream during the timed region) and the CPU oracle timed on the host.
+sigma=1e-2, nu=1/p), in the paper's arithmetic: fp64 storage, fp64
+matrix-core products, fp64 reductions and assembly (--prec selects fp32 or
+the 16-bit products instead).  Inputs are resident in device memory before
+the timed region starts.  The JSON line carries the throughput (evals/s),
+per-call duration quantiles, the rate of the same evaluation replayed from a
+captured graph, the roofline figures of the dominant kernel (timed with HIP
+events on its launch stream during the timed region) and the CPU oracle
+timed on the host.
 
+Legs of the default run:
+"precisions": the same evaluation in fp64, fp32, fp16 and bf16x3 products.
+"normx": ||X||^2 of the large data set.
+"small": d=3, n=10, r=3, p=750, fp64: one evaluation and 200 L-BFGS
+iterations from a Gaussian start.
+"mid": d=4, n=100, r=20, p=5000, fp64 and fp32: evaluation throughput, and a
+full solve (10 randomized-range-finder restarts) for each sigma in {1e-4,
+1e-3, 1e-2, 1e-1} with its relative error and similarity score.
 "batched": 512 problems, n ~ U{16..256}, r ~ U{2..32}, p = 250 r, d in
 {3, 4}, sigma in {1e-3, 1e-2}, 4 randomized-range-finder restarts each, fp32,
-solved together by symtd_solve_batched; solves/s against the plain loop of
-symtd_solve calls on a sample of the same problems, with the final relative
-errors of both.
-
+solved together by symtd_solve_batched, against the plain loop of
+symtd_solve calls on the same problems, with per-problem error differences.
 "served": Poisson arrivals (200 requests/s) of problems drawn the same way to
 a symtd_server; p50/p99 latency (arrival to result) and solves/s, against
 the plain first-in-first-out loop of symtd_solve calls replaying the same
 arrival trace.
 
-    python bench.py [--steps K] [--warmup W] [--prec fp32|fp64] [--no-cpu-baseline]
-                    [--only-fg] [--batched N] [--served N]
+    python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|fp16|bf16x3]
+                    [--no-cpu-baseline] [--only-fg] [--batched N] [--served N]
 """
 
 from __future__ import annotations
@@ -40,6 +49,8 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 WORKLOAD = dict(d=3, n=1000, r=100, p=100_000, sigma=1e-2)
+SMALL = dict(d=3, n=10, r=3, p=750, sigma=1e-2)
+MID = dict(d=4, n=100, r=20, p=5000)
 # MI355X published dense matrix-core peaks (TFLOP/s) and HBM bandwidth (GB/s)
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "fp16": 2500.0}
 PEAK_HBM_GBS = 8000.0
@@ -81,14 +92,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--prec", choices=["fp32", "fp64", "fp16", "bf16x3"], default="fp32")
+    ap.add_argument("--prec", choices=["fp32", "fp64", "fp16", "bf16x3"], default="fp64")
+    ap.add_argument("--pgtol", type=float, default=1e-6,
+                    help="gradient tolerance (of f / alpha) of the batched, served and mid-size solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--g1-blocks", type=int, default=0)
     ap.add_argument("--g2-splits", type=int, default=0)
     ap.add_argument("--only-fg", action="store_true", help="headline only (no batched/served legs)")
     ap.add_argument("--batched", type=int, default=512, help="problems of the batched leg")
-    ap.add_argument("--loop-sample", type=int, default=32, help="problems the per-problem loop solves")
     ap.add_argument("--served", type=int, default=600, help="requests of the served leg")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the served leg (requests/s)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -108,28 +120,48 @@ def calibrate_copy():
 
 
 def cpu_baseline(V64, nu, A64, lam, d, seconds):
-    """The fp64 oracle on the host cores, repeated for about `seconds`."""
+    """The fp64 oracle on the host cores, repeated for about `seconds`, and
+    on one thread for about a third of that."""
     from oracle.fg import fg_implicit
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([int(i.get("num_threads", 0)) for i in threadpool_info()] or [os.cpu_count()])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count()
-    fg_implicit(V64, nu, A64, lam, d, 0.0, with_intermediates=False)   # first touch
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        fg_implicit(V64, nu, A64, lam, d, 0.0, with_intermediates=False)
-        k += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": k / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{k} full fp64 evaluations of the same workload on the host ({dt:.1f} s)"}
+
+    def rate(budget):
+        fg_implicit(V64, nu, A64, lam, d, 0.0, with_intermediates=False)   # first touch
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            fg_implicit(V64, nu, A64, lam, d, 0.0, with_intermediates=False)
+            k += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return k, time.perf_counter() - t0
+
+    k, dt = rate(seconds)
+    out = {"value": k / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+           "sample": f"{k} full fp64 evaluations of the same workload on the host ({dt:.1f} s)"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            k1, dt1 = rate(seconds / 3)
+        out["one_thread"] = {"value": k1 / dt1, "unit": "evals/s", "cores": 1,
+                             "sample": f"{k1} evaluations on one thread ({dt1:.1f} s)"}
+    try:
+        import subprocess
+        model = [ln.split(":", 1)[1].strip() for ln in subprocess.run(["lscpu"], capture_output=True, text=True)
+                 .stdout.splitlines() if ln.startswith("Model name")]
+        if model:
+            out["cpu_model"] = model[0]
+    except Exception:
+        pass
+    return out
 
 
-def grouped_problems(count, key, restarts=4):
-    """Problems of the grouped workload (device tensors), and their shapes."""
+def grouped_problems(count, key, pgtol, restarts=4):
+    """Problems of the grouped workload (device tensors) and their sigmas."""
     import torch
 
     import paper_1911_03813_amd as S
@@ -138,19 +170,38 @@ def grouped_problems(count, key, restarts=4):
     for i, s in enumerate(shapes):
         V, nu, _ = synth.gmm(s["n"], s["r"], s["p"], s["sigma"], key, i)
         probs.append(dict(V=S.colmajor(torch.from_numpy(V).float()).cuda(), nu=torch.from_numpy(nu).cuda(),
-                          d=s["d"], r=s["r"], restarts=restarts, seed=1000 + i, pgtol=1e-4))
-    return probs
+                          d=s["d"], r=s["r"], restarts=restarts, seed=1000 + i, pgtol=pgtol))
+    return probs, np.array([s["sigma"] for s in shapes])
 
 
-def rel_err_summary(rel):
+def rel_err_summary(rel, sigma=None):
     """Final relative errors of a set of solves.  Their distribution is
-    bimodal on this workload (a solve either reaches about 1e-3 or stops in a
-    local minimum near 0.2), so the median alone moves with a few problems:
-    quantiles and the fraction below 1e-2 go with it."""
+    bimodal on this workload (a solve either reaches the noise floor of its
+    sigma or stops in a local minimum near 0.2), so the median alone moves
+    with a few problems: quantiles, the fraction below 1e-2 and the fraction
+    reaching 1e-4 (per sigma: the floor of sigma = 1e-2 lies above 1e-4)
+    go with it."""
     rel = np.asarray(rel, dtype=np.float64)
-    return {"median": float(np.median(rel)),
-            "q10_q50_q90": [float(x) for x in np.quantile(rel, [0.1, 0.5, 0.9])],
-            "frac_below_1e-2": float(np.mean(rel < 1e-2))}
+    out = {"median": float(np.median(rel)),
+           "q10_q50_q90": [float(x) for x in np.quantile(rel, [0.1, 0.5, 0.9])],
+           "frac_below_1e-2": float(np.mean(rel < 1e-2)),
+           "frac_at_most_1e-4": float(np.mean(rel <= 1e-4))}
+    if sigma is not None:
+        out["frac_at_most_1e-4_by_sigma"] = {f"{sg:g}": float(np.mean(rel[sigma == sg] <= 1e-4))
+                                             for sg in sorted(set(sigma.tolist()))}
+    return out
+
+
+def delta_summary(a, b):
+    """Per-problem |rel_err_a - rel_err_b| of the same problems solved two ways."""
+    dlt = np.abs(np.asarray(a) - np.asarray(b))
+    return {"q50_q90_q99_max": [float(x) for x in np.quantile(dlt, [0.5, 0.9, 0.99, 1.0])],
+            "frac_within_1e-4": float(np.mean(dlt <= 1e-4))}
+
+
+def exit_histogram(S, results):
+    names = [S.EXIT_NAMES.get(int(r["exit_reason"]), str(r["exit_reason"])) for r in results]
+    return {k: names.count(k) for k in sorted(set(names))}
 
 
 def loop_solve(S, ctx, pr):
@@ -251,35 +302,109 @@ def precision_leg(S, ctx, Vs, nu, As, lam, d, steps, warmup):
     return out
 
 
-def batched_leg(S, ctx, count, sample):
+def small_leg(S, ctx):
+    """d=3, n=10, r=3, p=750 (sigma 1e-2), fp64: one evaluation at a
+    Gaussian start (normalised columns, lambda = 1), then 200 L-BFGS
+    iterations from it, timed (no other stopping test)."""
     import torch
-    probs = grouped_problems(count, 4)
+    W = SMALL
+    V, nu, means = synth.gmm(W["n"], W["r"], W["p"], W["sigma"], 11)
+    A0 = synth.gauss_factors(W["n"], W["r"], 11, 5)
+    Vd = S.colmajor(torch.from_numpy(V)).cuda()
+    nud = torch.from_numpy(nu).cuda()
+    A0d = S.colmajor(torch.from_numpy(A0)).cuda()
+    lam = torch.ones(W["r"], dtype=torch.float64, device="cuda")
+    out = S.symtd_fg(ctx, Vd, nud, A0d, lam, W["d"], 0.0)
+    kw = dict(prec=S.PREC_FP64, pgtol=0.0, ftol=0.0, max_iters=200, restarts=1, init=S.INIT_GAUSS, A0=A0d)
+    S.symtd_solve(ctx, Vd, nud, W["d"], W["r"], **kw)          # warm
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S.symtd_fg(ctx, Vd, nud, A0d, lam, W["d"], 0.0, out=out)
+    torch.cuda.synchronize()
+    fg_s = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    res = S.symtd_solve(ctx, Vd, nud, W["d"], W["r"], **kw)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    return {"workload": "d=3 n=10 r=3 p=750 sigma=1e-2, fp64, Gaussian start, 200 L-BFGS iterations",
+            "fg_us": 1e6 * fg_s, "solve_ms": 1e3 * solve_s, "iters": int(res["iters"]), "evals": int(res["evals"]),
+            "exit": S.EXIT_NAMES.get(int(res["exit_reason"])), "rel_err": float(res["rel_err"]),
+            "score": S.metrics.similarity_score(means, res["A"].cpu().double().numpy())}
+
+
+def mid_leg(S, ctx, pgtol, steps=100):
+    """d=4, n=100, r=20, p=5000: evaluation throughput in fp64 and fp32, and
+    a solve with 10 randomized-range-finder restarts for each sigma, with its
+    relative error (fp64 evaluation at the final point) and the similarity
+    score of the recovered factors against the true means."""
+    import torch
+    W = MID
+    out = {"workload": "d=4 n=100 r=20 p=5000, Gaussian mixture, 10 RRF restarts", "fg": {}, "solves": []}
+    for name, prec, dt in (("fp64", S.PREC_FP64, torch.float64), ("fp32", S.PREC_FP32, torch.float32)):
+        V, nu, _ = synth.gmm(W["n"], W["r"], W["p"], 1e-2, 12)
+        A = synth.gauss_factors(W["n"], W["r"], 12, 5)
+        Vd = S.colmajor(torch.from_numpy(V).to(dt)).cuda()
+        Ad = S.colmajor(torch.from_numpy(A).to(dt)).cuda()
+        nud = torch.from_numpy(nu).cuda()
+        lam = torch.ones(W["r"], dtype=torch.float64, device="cuda")
+        res = S.symtd_fg(ctx, Vd, nud, Ad, lam, W["d"], 0.0)
+        for _ in range(10):
+            S.symtd_fg(ctx, Vd, nud, Ad, lam, W["d"], 0.0, out=res)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            S.symtd_fg(ctx, Vd, nud, Ad, lam, W["d"], 0.0, out=res)
+        torch.cuda.synchronize()
+        out["fg"][name] = {"evals_per_s": steps / (time.perf_counter() - t0)}
+    for k, sigma in enumerate((1e-4, 1e-3, 1e-2, 1e-1)):
+        V, nu, means = synth.gmm(W["n"], W["r"], W["p"], sigma, 13, k)
+        for name, prec, dt in (("fp64", S.PREC_FP64, torch.float64), ("fp32", S.PREC_FP32, torch.float32)):
+            Vd = S.colmajor(torch.from_numpy(V).to(dt)).cuda()
+            nud = torch.from_numpy(nu).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = S.symtd_solve(ctx, Vd, nud, W["d"], W["r"], prec=prec, restarts=10, seed=50 + k, pgtol=pgtol)
+            torch.cuda.synchronize()
+            out["solves"].append({"sigma": sigma, "precision": name, "seconds": time.perf_counter() - t0,
+                                  "rel_err": float(res["rel_err"]), "iters": int(res["iters"]),
+                                  "evals": int(res["evals"]), "exit": S.EXIT_NAMES.get(int(res["exit_reason"])),
+                                  "score": S.metrics.similarity_score(means, res["A"].cpu().double().numpy())})
+    return out
+
+
+def batched_leg(S, ctx, count, pgtol):
+    import torch
+    probs, sigma = grouped_problems(count, 4, pgtol)
     S.symtd_solve_batched(ctx, probs[:4])              # warm the path
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = S.symtd_solve_batched(ctx, probs)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    sample = min(sample, count)
+    # the plain loop of symtd_solve calls on every problem of the batch
     t0 = time.perf_counter()
-    lo = [loop_solve(S, ctx, pr) for pr in probs[:sample]]
+    lo = [loop_solve(S, ctx, pr) for pr in probs]
     torch.cuda.synchronize()
     tl = time.perf_counter() - t0
     rb = np.array([r["rel_err"] for r in res])
     rl = np.array([r["rel_err"] for r in lo])
     return {"workload": f"{count} problems n~U{{16..256}} r~U{{2..32}} p=250r d in {{3,4}} sigma in {{1e-3,1e-2}}, "
-                        "4 restarts, fp32", "solves_per_s": count / tb, "restart_solves_per_s": 4 * count / tb,
+                        f"4 restarts, fp32, pgtol {pgtol:g}",
+            "solves_per_s": count / tb, "restart_solves_per_s": 4 * count / tb,
             "seconds": tb, "steps": int(res[0]["steps"]),
-            "loop": {"problems": sample, "solves_per_s": sample / tl, "seconds": tl},
-            "speedup_vs_loop": (count / tb) / (sample / tl),
-            "rel_err": rel_err_summary(rb), "rel_err_loop_sample": rel_err_summary(rl),
-            "rel_err_batched_same_sample": rel_err_summary(rb[:sample]),
+            "loop": {"problems": count, "solves_per_s": count / tl, "seconds": tl},
+            "speedup_vs_loop": tl / tb,
+            "rel_err": rel_err_summary(rb, sigma), "rel_err_loop": rel_err_summary(rl, sigma),
+            "rel_err_abs_diff_vs_loop": delta_summary(rb, rl),
+            "exit": exit_histogram(S, res), "exit_loop": exit_histogram(S, lo),
             "evals_median": float(np.median([r["evals"] for r in res]))}
 
 
-def served_leg(S, ctx, count, rate):
+def served_leg(S, ctx, count, rate, pgtol):
     import torch
-    probs = grouped_problems(count, 5)
+    probs, sigma = grouped_problems(count, 5, pgtol)
     arrivals = synth.poisson_arrivals(rate, count, 5)
     warm = count // 10
     srv = S.Server(0, torch.float32, memory_bytes=16 << 30)
@@ -302,13 +427,21 @@ def served_leg(S, ctx, count, rate):
         stats = srv.stats()
     finally:
         srv.close()
+    order = sorted(sub, key=sub.get)
     # latency from the arrival of a request (its submit) to its result, on the server clock
-    lat = np.array([got[k]["t_done"] - got[k]["t_submit"] for k in sorted(sub, key=sub.get)])
-    done_t = np.array([got[k]["t_done"] for k in sorted(sub, key=sub.get)])
-    sub_t = np.array([got[k]["t_submit"] for k in sorted(sub, key=sub.get)])
+    lat = np.array([got[k]["t_done"] - got[k]["t_submit"] for k in order])
+    done_t = np.array([got[k]["t_done"] for k in order])
+    sub_t = np.array([got[k]["t_submit"] for k in order])
+    admit_t = np.array([got[k]["t_admit"] for k in order])
     meas = slice(warm, count)
     span = done_t[meas].max() - sub_t[meas].min()
-    rel = np.array([got[k]["rel_err"] for k in sorted(sub, key=sub.get)])
+    rel = np.array([got[k]["rel_err"] for k in order])
+    # requests on the device at once, from the admission and completion times
+    ev = sorted([(t, 1) for t in admit_t] + [(t, -1) for t in done_t], key=lambda e: (e[0], e[1]))
+    cur = peak = 0
+    for _, k in ev:
+        cur += k
+        peak = max(peak, cur)
     # the plain loop: each request solved alone in arrival order (FIFO), service times measured
     service = []
     for pr in probs:
@@ -326,16 +459,62 @@ def served_leg(S, ctx, count, rate):
     lat_loop = np.array(lat_loop)
     rel_loop = np.array([s[1] for s in service])
     span_loop = free_at - arrivals[warm]
-    return {"workload": f"{count} requests, Poisson {rate:g}/s, problems as the batched leg, 4 restarts, fp32 "
-                        f"(first {warm} excluded)",
+    return {"workload": f"{count} requests, Poisson {rate:g}/s, problems as the batched leg, 4 restarts, fp32, "
+                        f"pgtol {pgtol:g} (first {warm} excluded)",
             "p50_ms": 1e3 * float(np.percentile(lat[meas], 50)), "p99_ms": 1e3 * float(np.percentile(lat[meas], 99)),
-            "solves_per_s": (count - warm) / span,
+            "solves_per_s": (count - warm) / span, "peak_requests_on_device": peak,
             "loop": {"p50_ms": 1e3 * float(np.percentile(lat_loop[meas], 50)),
                      "p99_ms": 1e3 * float(np.percentile(lat_loop[meas], 99)),
                      "solves_per_s": (count - warm) / span_loop,
                      "mean_service_ms": 1e3 * float(np.mean([s[0] for s in service]))},
-            "rel_err": rel_err_summary(rel[meas]), "rel_err_loop": rel_err_summary(rel_loop[meas]),
+            "rel_err": rel_err_summary(rel[meas], sigma[meas]), "rel_err_loop": rel_err_summary(rel_loop[meas],
+                                                                                              sigma[meas]),
+            "rel_err_abs_diff_vs_loop": delta_summary(rel[meas], rel_loop[meas]),
             "steps": int(stats["steps"])}
+
+
+def call_stats(evaluate, calls):
+    """Durations of single evaluations, each bracketed by events on the
+    stream the library launches on (the current stream)."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for a, b in ev:
+        a.record()
+        evaluate()
+        b.record()
+    torch.cuda.synchronize()
+    us = np.array([1e3 * a.elapsed_time(b) for a, b in ev])
+    return {"calls": calls, "p10_us": float(np.percentile(us, 10)), "median_us": float(np.median(us)),
+            "p90_us": float(np.percentile(us, 90))}
+
+
+def graph_rate(evaluate, out, steps):
+    """The evaluation captured once as a graph and replayed: evals/s, and
+    whether every replay gives the eager bits."""
+    import torch
+    evaluate()
+    torch.cuda.synchronize()
+    ref = [x.clone() for x in out]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        evaluate()                               # warm on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        evaluate()
+    g.replay()
+    torch.cuda.synchronize()
+    same = all(torch.equal(x, y) for x, y in zip(out, ref))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    same = same and all(torch.equal(x, y) for x, y in zip(out, ref))
+    del g
+    return {"evals_per_s": 1.0 / sec, "ms_per_eval": 1e3 * sec, "replays": steps, "replays_equal_eager": same}
 
 
 def main():
@@ -416,6 +595,9 @@ def main():
     torch.cuda.synchronize()
     S.symtd_profile_enable(ctx, False)
     breakdown = read_profile(bsteps)
+    # per-call duration quantiles, and the evaluation replayed from a graph
+    calls = call_stats(evaluate, max(20, args.steps))
+    graph = graph_rate(evaluate, out, max(20, args.steps))
 
     sec = (t1 - t0) / args.steps
     evals = 1.0 / sec
@@ -459,22 +641,29 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16", "bf16x3": "bf16x3"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "large single instance: Gaussian mixture d=3 n=1000 r=100 p=100000 sigma=1e-2",
-                   "d": d, "n": n, "r": r, "p": p, "precision": args.prec, "storage": args.prec},
+                   "d": d, "n": n, "r": r, "p": p, "precision": args.prec,
+                   "storage": "fp64" if args.prec == "fp64" else "fp32"},
         "step_mfma_frac": mult * flop_step * evals / (peak * 1e12),
         "roofline": roof,
         "kernels_us_per_step": {k: round(v["step_us"], 2) for k, v in breakdown.items()},
         "kernels_us_per_step_note": f"every kernel, timed over {bsteps} steps after the timed region",
+        "per_call": calls,
+        "graph_replay": graph,
     }
     if data is not None:
         data.close()
     del Vd, Ad, out
-    if not args.only_fg and args.prec == "fp32":
-        res["precisions"] = precision_leg(S, ctx, Vs, nu, As, lam, d, args.steps, args.warmup)
-        res["normx"] = normx_leg(S, ctx, Vs, nu, d)
+    if not args.only_fg:
+        V32 = V.astype(np.float32).astype(np.float64)
+        A32 = A.astype(np.float32).astype(np.float64)
+        res["precisions"] = precision_leg(S, ctx, V32, nu, A32, lam, d, args.steps, args.warmup)
+        res["normx"] = normx_leg(S, ctx, V32, nu, d)
+        res["small"] = small_leg(S, ctx)
+        res["mid"] = mid_leg(S, ctx, args.pgtol)
         if args.batched > 0:
-            res["batched"] = batched_leg(S, ctx, args.batched, args.loop_sample)
+            res["batched"] = batched_leg(S, ctx, args.batched, args.pgtol)
         if args.served > 0:
-            res["served"] = served_leg(S, ctx, args.served, args.rate)
+            res["served"] = served_leg(S, ctx, args.served, args.rate, args.pgtol)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(Vs, nu, As, lam, d, args.cpu_seconds)
     ctx.close()

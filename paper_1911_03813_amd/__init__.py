@@ -626,3 +626,6 @@ def profile_names():
             return out
         out.append(s)
         i += 1
+
+
+from . import metrics  # noqa: E402,F401  (host-side quality measures of solve results)

@@ -119,6 +119,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   const int64_t u0 = blk * U / B, u1 = (blk + 1) * U / B;
   const int tg = a.col0 >> 4;
   const int dm1 = a.d - 1;
+  const int epoch = handoff_epoch(a.ho.epoch);
 
   acc_t acc[MT][NT];
 #pragma unroll
@@ -330,11 +331,12 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
           }
         xput_complete();   // each wave's stores are done (visible device-wide)
         __syncthreads();   // ... before the flag is raised
-        if (tid == 0) __hip_atomic_store(a.ho.flag + blk, a.ho.put, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.ho.flag + blk, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         if (ke < KC) {
           // the next block holds chunks [ke, KC) of this slab
-          xwait_flag(a.ho.flag + blk + 1, a.ho.want, a.ho.err, a.ho.spin_limit);
+          xwait_flag(a.ho.flag + blk + 1, (a.ho.spin >> 31) ? (epoch | 0x40000000) : epoch, a.ho.err,
+                     (int)(a.ho.spin & 0x7fffffffu));
           const T* pp = a.part + opaque_uniform(blk + 1) * PART + (int64_t)wave * (MT * NT * 4 * 64);
 #pragma unroll
           for (int m = 0; m < MT; ++m)
@@ -345,6 +347,12 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) acc[m][t][v] += q4.e[v];
             }
+          // every wave has read the partial; the flag is lowered (the epoch
+          // tags do not need it, but with the store in place the compiler
+          // does not overlap the partial's loads with the epilogue, which
+          // made the fp64 kernel spill 59 registers)
+          __syncthreads();
+          if (tid == 0) __hip_atomic_store(a.ho.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // epilogue: acc[m][t][v] = z at l = 16 b + row(g, v), j = col0 + 16t + c.
         // w = nu z^(d-1) in the storage precision, the power taken over all
@@ -398,6 +406,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
     s += __shfl_xor(s, 32);
     if (g == 0) a.wpart[(blk * NW + wave) * (int64_t)a.rp + a.col0 + 16 * t + c] = s;
   }
+  handoff_done(a.ho.epoch, B, epoch);
 }
 
 // ---------------------------------------------------------------------------

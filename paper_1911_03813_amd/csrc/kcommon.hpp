@@ -176,6 +176,32 @@ __device__ __forceinline__ int64_t opaque_uniform(int64_t x) {
   return x;
 }
 
+// The epoch of a split-product launch, in [1, 2^30): every block reads the
+// stored word (+1) when it starts, and the last block to finish advances it
+// (handoff_done), so consecutive launches, graph replays included, never
+// share an epoch.  The next launch on the stream starts only after the last
+// block has stored the new value.
+// One thread reads the word and the block shares it through LDS, so every
+// wave holds the same value before any block can have arrived at its end.
+__device__ __forceinline__ int handoff_epoch(const int* word) {
+  __shared__ int e;
+  if (threadIdx.x == 0) e = 1 + __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(e);
+}
+// Called by every block at its very end.  The block's last arrival (the
+// launch's last block) resets the counter and stores the next epoch.
+// word[0] is the epoch word, word[1] the arrival counter.
+__device__ __forceinline__ void handoff_done(int* word, int64_t nblocks, int epoch) {
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (__hip_atomic_fetch_add(word + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (int)nblocks - 1) {
+      __hip_atomic_store(word + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(word, epoch >= 0x3fffffff ? 0 : epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // Spin until a hand-off flag holds `want` (relaxed device-scope loads),
 // giving up after `limit` polls that did not see it: then *err (a word of
 // pinned host memory that the host checks at its next call) is set and the

@@ -45,15 +45,16 @@ template <typename T> constexpr int g1_waves() { return sizeof(T) == 8 ? 8 : G1_
 constexpr int G2_STAGES_F32 = 3;
 constexpr int G2_STAGES_F64 = 2;
 
-// Stream-K hand-off of a split product: flag[b] is raised to `put` by block
-// b once its partial is published; block b-1 waits for it to read `want`
-// (normally put: the launch's epoch, unique per launch and never 0) for at
-// most `spin_limit` polls, after which it sets *err (pinned host memory).
+// Stream-K hand-off of a split product: flag[b] is raised to the launch's
+// epoch (handoff_epoch) by block b once its partial is published; block b-1
+// waits for that value for at most `spin` polls (bits 0-30), after which it
+// sets *err (pinned host memory).  With bit 31 of `spin` set (testing) it
+// waits for a value that no block writes.
 struct Handoff {
   int* flag;       // [blocks] hand-off flags
   int* err;        // device address of the context's error word
-  int put, want;
-  int spin_limit;
+  int* epoch;      // the context's epoch word, then its arrival counter (zero at creation)
+  unsigned spin;
 };
 
 template <typename T>

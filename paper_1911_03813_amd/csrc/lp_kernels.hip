@@ -221,6 +221,7 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
   const E* V = (const E*)a.Vc;
   const E* Ac = (const E*)a.Ac;
   const int dm1 = a.d - 1;
+  const int epoch = handoff_epoch(a.ho.epoch);
 
   f4 acc[LP_MT][NT];
 #pragma unroll
@@ -272,16 +273,19 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
             xput4(pp + ((m * NT + t) * 64 + lane) * 4, acc[m][t]);
         xput_complete();   // each wave's stores are done (visible device-wide)
         __syncthreads();   // ... before the flag is raised
-        if (tid == 0) __hip_atomic_store(a.ho.flag + blk, a.ho.put, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.ho.flag + blk, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         // owner (nl holds the slab's weights, loaded when the slab began)
         if (ke < KC) {
-          xwait_flag(a.ho.flag + blk + 1, a.ho.want, a.ho.err, a.ho.spin_limit);
+          xwait_flag(a.ho.flag + blk + 1, (a.ho.spin >> 31) ? (epoch | 0x40000000) : epoch, a.ho.err,
+                     (int)(a.ho.spin & 0x7fffffffu));
           const float* pp = a.part + (blk + 1) * PART + (int64_t)wave * (LP_MT * NT * 256);
   #pragma unroll
           for (int m = 0; m < LP_MT; ++m)
   #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] += xget4v(pp + ((m * NT + t) * 64 + lane) * 4);
+          __syncthreads();   // read by every wave; the flag is lowered as in the fp32 / fp64 kernel
+          if (tid == 0) __hip_atomic_store(a.ho.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // epilogue: acc[m][t][v] = z at l = lb + v, column col0 + 16 t + c.
         // w = nu z^(d-1) in fp32 (its 16-bit storage rounds far more); the
@@ -367,6 +371,7 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
     s += __shfl_xor(s, 32);
     if (g == 0) a.wpart[(blk * LP_WAVES + wave) * (int64_t)a.rp + a.col0 + 16 * t + c] = s;
   }
+  handoff_done(a.ho.epoch, B, epoch);
 }
 
 // ---------------------------------------------------------------------------

@@ -102,13 +102,12 @@ void symtd_ctx::prof_end(int which, hipStream_t st) {
 }
 
 symtd::Handoff symtd_ctx::handoff() {
-  if (++epoch > 0x3fffffffu) epoch = 1;   // never 0 (the flags' initial value)
   symtd::Handoff h;
   h.flag = flags;
   h.err = err_dev;
-  h.put = (int)epoch;
-  h.want = tune_fault ? (int)(epoch | 0x40000000u) : (int)epoch;   // the former is never written
-  h.spin_limit = tune_spin > 0 ? (int)std::min<int64_t>(tune_spin, 0x7fffffff) : (1 << 24);
+  h.epoch = epoch_word;
+  h.spin = (unsigned)(tune_spin > 0 ? std::min<int64_t>(tune_spin, 0x7fffffff) : (1 << 24)) |
+           (tune_fault ? 0x80000000u : 0u);
   return h;
 }
 
@@ -556,7 +555,7 @@ symtd_status symtd_create(int device, symtd_ctx** out) {
   c->cu_count = prop.multiProcessorCount;
   // flags and the arrival counters in one zeroed allocation; the error word
   // in pinned, device-mapped host memory
-  const size_t words = 4 * (size_t)c->cu_count + symtd_ctx::kFinalCounters;
+  const size_t words = 4 * (size_t)c->cu_count + symtd_ctx::kFinalCounters + 2;
   if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->flags, sizeof(int) * words) != hipSuccess ||
       hipMemset(c->flags, 0, sizeof(int) * words) != hipSuccess ||
       hipHostMalloc((void**)&c->err_host, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
@@ -569,6 +568,7 @@ symtd_status symtd_create(int device, symtd_ctx** out) {
   *c->err_host = 0;
   c->nflags = 4 * c->cu_count;  // >= the blocks of any split product
   c->final_count = c->flags + c->nflags;
+  c->epoch_word = c->final_count + symtd_ctx::kFinalCounters;
   if (scratch_address(c, device) != SYMTD_OK) {
     symtd_destroy(c);
     return SYMTD_EDEVICE;

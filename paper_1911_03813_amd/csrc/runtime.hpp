@@ -29,7 +29,7 @@ struct symtd_ctx {
   int nflags = 0;
   int* final_count = nullptr;
   static constexpr int kFinalCounters = 1024;
-  uint32_t epoch = 0;        // of the last split-product launch
+  int* epoch_word = nullptr;  // the split products' launch epoch and arrival counter (2 words)
   // error word in pinned host memory: a kernel whose hand-off wait gave up
   // sets it (err_dev is its device address); every call checks it first
   int* err_host = nullptr;
@@ -54,7 +54,7 @@ struct symtd_ctx {
   symtd_status set_device();
   symtd_status check_common(symtd_dtype dt, const void* V, int64_t ldv, const double* nu,
                             int64_t n, int64_t p, int d);
-  // hand-off arguments of the next split-product launch (a fresh epoch)
+  // hand-off arguments of a split-product launch
   symtd::Handoff handoff();
   // SYMTD_EDEVICE (and the word cleared) if a kernel set the error word
   symtd_status take_device_error();

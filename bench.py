@@ -62,11 +62,11 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
                    "paper_1911_03813_amd/csrc/kcommon.hpp", "paper_1911_03813_amd/csrc/lp_kernels.hip",
                    "paper_1911_03813_amd/csrc/lp.hpp")
-TRAFFIC_SHA = "492653ad056b681b"
-TRAFFIC_BYTES = {("fp32", "gemm1"): 506.6e6, ("fp32", "gemm2"): 475.3e6,
-                 ("fp64", "gemm1"): 1094.2e6, ("fp64", "gemm2"): 948.5e6,
-                 ("fp16", "gemm1"): 269.6e6, ("fp16", "gemm2"): 237.5e6,
-                 ("bf16x3", "gemm1"): 501.7e6, ("bf16x3", "gemm2"): 460.1e6}
+TRAFFIC_SHA = "24cc126df2bade14"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 506.4e6, ("fp32", "gemm2"): 475.4e6,
+                 ("fp64", "gemm1"): 1089.4e6, ("fp64", "gemm2"): 948.5e6,
+                 ("fp16", "gemm1"): 269.6e6, ("fp16", "gemm2"): 237.6e6,
+                 ("bf16x3", "gemm1"): 501.8e6, ("bf16x3", "gemm2"): 460.1e6}
 
 
 def traffic_for(prec, kernel):

@@ -24,6 +24,8 @@ Anal. Appl., 2020; arXiv 1911.03813):
 * ``philox``  - the Philox-4x32-10 counter-based generator and Box-Muller
   normals, written from their published definitions, for starts drawn on
   the device.
+* ``stochastic`` - the sampled objective of Section 5 (Lemma 5.1) and Adam
+  with the paper's epoch, learning-rate and restore schedule.
 
 Pins (tests marked "not gpu") tie every function to something other than
 itself: brute force on explicit tensors, closed forms, invariants and

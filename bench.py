@@ -20,6 +20,9 @@ iterations from a Gaussian start.
 "mid": d=4, n=100, r=20, p=5000, fp64 and fp32: evaluation throughput, and a
 full solve (10 randomized-range-finder restarts) for each sigma in {1e-4,
 1e-3, 1e-2, 1e-1} with its relative error and similarity score.
+"stochastic": Section 5's comparison at d=3, n=500, r=10, p=500,000,
+sigma=0.1: L-BFGS on the full data against Adam on s in {10, 100, 1000}
+sampled columns per step, from the same ten starts.
 "batched": 512 problems, n ~ U{16..256}, r ~ U{2..32}, p = 250 r, d in
 {3, 4}, sigma in {1e-3, 1e-2}, 4 randomized-range-finder restarts each, fp32,
 solved together by symtd_solve_batched, against the plain loop of
@@ -96,6 +99,7 @@ def parse():
     ap.add_argument("--pgtol", type=float, default=1e-6,
                     help="gradient tolerance (of f / alpha) of the batched, served and mid-size solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stoch", action="store_true", help="skip the stochastic (Adam) comparison leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--g1-blocks", type=int, default=0)
     ap.add_argument("--g2-splits", type=int, default=0)
@@ -371,6 +375,45 @@ def mid_leg(S, ctx, pgtol, steps=100):
                                   "rel_err": float(res["rel_err"]), "iters": int(res["iters"]),
                                   "evals": int(res["evals"]), "exit": S.EXIT_NAMES.get(int(res["exit_reason"])),
                                   "score": S.metrics.similarity_score(means, res["A"].cpu().double().numpy())})
+    return out
+
+
+def stoch_leg(S, ctx, pgtol):
+    """The comparison of Section 5 (Table stoch): d=3, n=500, r=10,
+    p=500,000, sigma=0.1, fp32.  The standard method (L-BFGS on the full
+    data) and Adam on s sampled columns per step (s in {10, 100, 1000},
+    the paper's schedule), each from the same 10 randomized-range-finder
+    starts, all restarts of a method run together; the shifted objective
+    (alpha = 0) of the best restart, its similarity score and the wall time
+    of all ten runs."""
+    import torch
+    n, r, p, d = 500, 10, 500_000, 3
+    V, nu, means = synth.gmm(n, r, p, 0.1, 14, congruent=True)   # the paper's means: pairwise cosine 0.5
+    Vd = S.colmajor(torch.from_numpy(V).float()).cuda()
+    nud = torch.from_numpy(nu).cuda()
+    del V
+    out = {"workload": "d=3 n=500 r=10 p=500000 sigma=0.1, congruent means, fp32, 10 RRF starts shared by all "
+                       "methods, shifted f",
+           "methods": []}
+
+    def row(name, sec, res, extra):
+        out["methods"].append({"method": name, "seconds": sec, "best_f_shifted": float(res["f"]),
+                               "score": S.metrics.similarity_score(means, res["A"].cpu().double().numpy()), **extra})
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = S.symtd_solve(ctx, Vd, nud, d, r, restarts=10, seed=41, pgtol=pgtol, alpha=0.0)
+    torch.cuda.synchronize()
+    row("standard (L-BFGS, full data)", time.perf_counter() - t0, res, {"iters": int(res["iters"]),
+                                                                      "evals": int(res["evals"])})
+    for s in (10, 100, 1000):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = S.symtd_solve_adam(ctx, Vd, nud, d, r, samples=s, restarts=10, seed=41)
+        torch.cuda.synchronize()
+        row(f"Adam, s={s}", time.perf_counter() - t0, res, {"epochs": int(res["epochs"]),
+                                                            "steps": int(res["iters"])})
+    del Vd
     return out
 
 
@@ -660,6 +703,8 @@ def main():
         res["normx"] = normx_leg(S, ctx, V32, nu, d)
         res["small"] = small_leg(S, ctx)
         res["mid"] = mid_leg(S, ctx, args.pgtol)
+        if not args.no_stoch:
+            res["stochastic"] = stoch_leg(S, ctx, args.pgtol)
         if args.batched > 0:
             res["batched"] = batched_leg(S, ctx, args.batched, args.pgtol)
         if args.served > 0:

@@ -294,6 +294,71 @@ symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb,
                          const symtd_solve_opts* opts, symtd_solve_result* out);
 
 /* ------------------------------------------------------------------------
+ * Stochastic objective and Adam (Section 5).
+ *
+ * For very many observations, the objective and gradient are estimated from
+ * s columns of V drawn uniformly with replacement (Lemma 5.1): Algorithm 2
+ * on the sampled columns with weights p nu_i / s (= 1/s for nu = 1/p) gives
+ * unbiased estimates of X a^{d-1}, and so of the shifted objective (alpha
+ * = 0) and its gradient, which are linear in X.
+ *
+ * Draws: sample k of draw t under `seed` is word k mod 4 of the
+ * Philox-4x32-10 block with counter (k / 4, t low word, t high word, 3) and
+ * key (seed low word, seed high word), mapped to column floor(x p / 2^32).
+ * ------------------------------------------------------------------------ */
+
+/* Shifted objective and gradient (alpha = 0) on draw `draw` of s samples.
+ * Arguments as in symtd_fg, plus s >= 1, seed, draw >= 0 and idx: NULL, or
+ * s int64 device values that receive the sampled column indices.  Uses the
+ * context's solver workspace for the gathered columns.  Asynchronous. */
+symtd_status symtd_fg_sampled(symtd_ctx* ctx, void* stream, symtd_dtype dt,
+                              const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
+                              int64_t s, uint64_t seed, int64_t draw,
+                              const void* A, int64_t lda, const double* lambda, int64_t r, int d,
+                              symtd_prec prec, double* f, double* g_lambda, void* G_A, int64_t ldg,
+                              int64_t* idx);
+
+/* Adam (Kingma & Ba, 2015) on the sampled shifted objective with the
+ * paper's schedule: epochs of epoch_len steps, each step on a fresh draw
+ * (draw t = steps taken before it; all restarts step together on the same
+ * draw); after every epoch the shifted objective is estimated on a fixed
+ * set of est_samples columns (draw 0 of Philox stream 4, same map).  If the
+ * estimate did not decrease, the state saved at the previous accepted epoch
+ * (x, the moments and the step count) is restored and the learning rate
+ * drops from lr0 to lr1; the second time the restart stops on that saved
+ * state.  Starts as in symtd_solve (seed, init, A0).  max_epochs caps the
+ * epochs. */
+typedef struct symtd_adam_opts {
+  symtd_prec prec;          /* SYMTD_PREC_FP64 or SYMTD_PREC_FP32, matching the storage */
+  int64_t samples;          /* s, columns per step (paper: 10, 100, 1000) */
+  int64_t est_samples;      /* columns of the fixed estimation set (paper: 1000) */
+  int epoch_len;            /* steps per epoch (paper: 100) */
+  int64_t max_epochs;
+  double lr0, lr1;          /* learning rates (paper: 0.01, then 0.001) */
+  double beta1, beta2, eps; /* Adam's constants (0.9, 0.999, 1e-8) */
+  int restarts;             /* 1 .. 1024 */
+  uint64_t seed;            /* starts and draws */
+  symtd_init init;
+  const void* A0;           /* optional starts, as in symtd_solve_opts */
+} symtd_adam_opts;
+
+/* Defaults: fp32, s = 100, 1000 estimation samples, epochs of 100, at most
+ * 1000 epochs, lr 0.01 then 0.001, beta 0.9 / 0.999, eps 1e-8, 1 restart,
+ * seed 0, RRF starts. */
+symtd_status symtd_adam_opts_default(symtd_adam_opts* opts);
+
+/* Result as in symtd_solve, with: f = the shifted objective (alpha = 0) of
+ * the best restart's final point on the whole data set (fp64 products); the
+ * best restart has the lowest shifted objective in working precision; alpha
+ * = 0, rel_err = NaN; iters = gradient steps, evals = epochs;
+ * exit_reason SYMTD_EXIT_FTOL (second epoch without decrease) or
+ * SYMTD_EXIT_MAX_ITERS (max_epochs); f_restarts the shifted objectives;
+ * f_trace the estimates (at the start, then after every epoch).
+ * Synchronous. */
+symtd_status symtd_solve_adam(symtd_ctx* ctx, void* stream, const symtd_problem* pb, const symtd_adam_opts* opts,
+                              symtd_solve_result* out);
+
+/* ------------------------------------------------------------------------
  * Batched forms: many independent problems of uneven shape at once.
  *
  * Every problem is one instance of the grouped kernels: each evaluation step

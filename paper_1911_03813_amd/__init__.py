@@ -91,6 +91,15 @@ class ServerStats(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("memory_used", ctypes.c_size_t), ("memory_bytes", ctypes.c_size_t)]
 
 
+class AdamOpts(ctypes.Structure):
+    """symtd_adam_opts"""
+    _fields_ = [("prec", ctypes.c_int), ("samples", ctypes.c_int64), ("est_samples", ctypes.c_int64),
+                ("epoch_len", ctypes.c_int), ("max_epochs", ctypes.c_int64), ("lr0", ctypes.c_double),
+                ("lr1", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("restarts", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("init", ctypes.c_int), ("A0", ctypes.c_void_p)]
+
+
 class SolveResult(ctypes.Structure):
     """symtd_solve_result"""
     _fields_ = [("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("lam", ctypes.c_void_p),
@@ -126,6 +135,10 @@ SIGNATURES = {
     "symtd_fg_data": (_int, [_vp, _vp, _vp, _vp, _i64, _vp, _i64, _int, _dbl, _vp, _vp, _vp, _i64]),
     "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
     "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
+    "symtd_fg_sampled": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _i64, _c.c_uint64, _i64, _vp, _i64,
+                                _vp, _i64, _int, _int, _vp, _vp, _vp, _i64, _vp]),
+    "symtd_adam_opts_default": (_int, [_c.POINTER(AdamOpts)]),
+    "symtd_solve_adam": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(AdamOpts), _c.POINTER(SolveResult)]),
     "symtd_fg_batched": (_int, [_vp, _vp, _int, _int, _i64, _c.POINTER(FgItem)]),
     "symtd_server_create": (_int, [_c.POINTER(ServerOpts), _c.POINTER(_vp)]),
     "symtd_server_submit": (_int, [_vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(_c.c_uint64)]),
@@ -169,6 +182,14 @@ class Context:
     """A symtd context on one HIP device (owns the device workspace)."""
 
     def __init__(self, device: int = 0):
+        # torch's GPU runtime must come up before the library's in the same
+        # process (torch finds no device otherwise); tensors are torch's
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         h = _vp()
         st = lib().symtd_create(device, ctypes.byref(h))
         if st != SYMTD_OK:
@@ -399,6 +420,85 @@ def symtd_solve(ctx: Context, V, nu, d: int, r: int, *, prec: int | None = None,
     return call.result()
 
 
+def symtd_fg_sampled(ctx: Context, V, nu, A, lam, d: int, s: int, seed: int, draw: int, prec: int | None = None,
+                     with_indices: bool = False, out=None, stream=None):
+    """Shifted objective and gradient on draw `draw` of s sampled columns
+    (Section 5, Lemma 5.1).  Returns (f, g_lambda, G_A[, indices])."""
+    import torch
+    Vp, ldv = _mat(V, "V")
+    Ap, lda = _mat(A, "A", V.dtype)
+    n, p = V.shape
+    r = A.shape[1]
+    if A.shape[0] != n:
+        raise ValueError("A must have as many rows as V")
+    if prec is None:
+        prec = PREC_FP64 if V.dtype == torch.float64 else PREC_FP32
+    if out is None:
+        f = torch.empty(1, dtype=torch.float64, device=V.device)
+        g = torch.empty(r, dtype=torch.float64, device=V.device)
+        G = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
+    else:
+        f, g, G = out
+    Gp, ldg = _mat(G, "G_A", V.dtype)
+    idx = torch.empty(s, dtype=torch.int64, device=V.device) if with_indices else None
+    st = lib().symtd_fg_sampled(ctx.handle, _stream(stream), _dt(V), Vp, ldv, _vec(nu, "nu", p), n, p, int(s),
+                                int(seed), int(draw), Ap, lda, _vec(lam, "lambda", r), r, int(d), int(prec),
+                                _vec(f, "f", 1), _vec(g, "g_lambda", r), Gp, ldg,
+                                idx.data_ptr() if idx is not None else None)
+    _check(ctx, st)
+    return (f, g, G, idx) if with_indices else (f, g, G)
+
+
+def symtd_solve_adam(ctx: Context, V, nu, d: int, r: int, *, samples: int = 100, est_samples: int = 1000,
+                     epoch_len: int = 100, max_epochs: int = 1000, lr0: float = 0.01, lr1: float = 0.001,
+                     beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, restarts: int = 1, seed: int = 0,
+                     init: int = None, A0=None, prec: int | None = None, trace_len: int = 0, stream=None):
+    """Adam on the sampled shifted objective with the paper's schedule
+    (symtd_solve_adam).  Returns a dict like symtd_solve's; f is the shifted
+    objective on the whole data set, f_trace the per-epoch estimates."""
+    import numpy as np
+    import torch
+    Vp, ldv = _mat(V, "V")
+    n, p = V.shape
+    if prec is None:
+        prec = PREC_FP64 if V.dtype == torch.float64 else PREC_FP32
+    pb = Problem(_dt(V), Vp, ldv, _vec(nu, "nu", p), n, p, int(d), int(r))
+    o = AdamOpts()
+    _check(None, lib().symtd_adam_opts_default(ctypes.byref(o)))
+    o.prec, o.samples, o.est_samples, o.epoch_len, o.max_epochs = int(prec), int(samples), int(est_samples), \
+        int(epoch_len), int(max_epochs)
+    o.lr0, o.lr1, o.beta1, o.beta2, o.eps = float(lr0), float(lr1), float(beta1), float(beta2), float(eps)
+    o.restarts, o.seed = int(restarts), int(seed)
+    o.init = INIT_RRF if init is None else int(init)
+    keep = [V, nu]
+    if A0 is not None:
+        A0p, lda0 = _mat(A0, "A0", V.dtype)
+        if tuple(A0.shape) != (n, restarts * r) or lda0 != n:
+            raise ValueError("A0 must be an n x (restarts*r) column-major tensor with leading dimension n")
+        o.A0 = A0p
+        keep.append(A0)
+    A = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
+    lam = torch.empty(r, dtype=torch.float64, device=V.device)
+    fr = np.zeros(restarts)
+    ir = np.zeros(restarts, dtype=np.int64)
+    er = np.zeros(restarts, dtype=np.int64)
+    xr = np.zeros(restarts, dtype=np.int32)
+    tr = np.zeros((restarts, max(trace_len, 1)))
+    res = SolveResult()
+    res.A, res.lda, res.lam = _mat(A, "A")[0], _mat(A, "A")[1], lam.data_ptr()
+    res.f_restarts = fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    res.iters_restarts = ir.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    res.evals_restarts = er.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    res.exit_restarts = xr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    res.f_trace = tr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if trace_len > 0 else None
+    res.trace_len = int(trace_len)
+    _check(ctx, lib().symtd_solve_adam(ctx.handle, _stream(stream), ctypes.byref(pb), ctypes.byref(o),
+                                       ctypes.byref(res)))
+    return {"A": A, "lam": lam, "f": res.f, "iters": res.iters, "epochs": res.evals, "exit_reason": res.exit_reason,
+            "best_restart": res.best_restart, "f_restarts": fr, "steps_restarts": ir, "epochs_restarts": er,
+            "exit_restarts": xr, "f_trace": tr[:, :trace_len] if trace_len > 0 else None}
+
+
 def symtd_solve_batched(ctx: Context, problems, stream=None):
     """symtd_solve for every problem (dicts with V, nu, d, r and symtd_solve's
     keyword options), all on the grouped engine.  Returns one result dict per
@@ -457,6 +557,12 @@ class Server:
         o = ServerOpts(int(device), dt, PREC_FP64 if dt == F64 else PREC_FP32, int(memory_bytes),
                        int(check_every), int(bool(use_graph)))
         h = _vp()
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         st = lib().symtd_server_create(ctypes.byref(o), ctypes.byref(h))
         if st != SYMTD_OK:
             raise SymtdError(st, "symtd_server_create failed")

@@ -71,6 +71,8 @@ def test_struct_layouts_match_header(tmp_path):
                                            "seed", "init", "alpha_mode", "alpha", "A0", "check_every"]),
         "symtd_fg_item": (S.FgItem, ["V", "ldv", "nu", "n", "p", "d", "A", "lda", "lambda", "r", "models",
                                      "alpha", "f", "g_lambda", "G_A", "ldg"]),
+        "symtd_adam_opts": (S.AdamOpts, ["prec", "samples", "est_samples", "epoch_len", "max_epochs", "lr0",
+                                         "lr1", "beta1", "beta2", "eps", "restarts", "seed", "init", "A0"]),
         "symtd_server_opts": (S.ServerOpts, ["device", "dt", "prec", "memory_bytes", "check_every", "use_graph"]),
         "symtd_server_result": (S.ServerResult, ["id", "status", "f", "alpha", "rel_err", "iters", "evals",
                                                  "exit_reason", "best_restart", "n", "r", "A", "lambda",

@@ -32,5 +32,5 @@ itself: brute force on explicit tensors, closed forms, invariants and
 textbook routines.
 """
 
-from .fg import fg_implicit, fg_bruteforce, grad_paper_explicit, magnitudes  # noqa: F401
+from .fg import fg_explicit, fg_implicit, fg_bruteforce, grad_paper_explicit, magnitudes, magnitudes_explicit  # noqa: F401
 from .normx import normx_implicit, normx_explicit  # noqa: F401

@@ -109,6 +109,25 @@ def grad_paper_explicit(V, nu, A, lam, d: int):
     return g, G
 
 
+def fg_explicit(X, A, lam, d: int, alpha: float = 0.0) -> FG:
+    """Algorithm 1 (fg_explicit) on a given dense symmetric X (n^d entries):
+    the TTSVs y_j = X a_j^{d-1} by eq. (ExpXbdd), w_j = a_j' y_j, then the
+    same closing lines as Algorithm 2."""
+    X = np.asarray(X, dtype=np.float64)
+    A = np.asarray(A, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    r = A.shape[1]
+    Y = np.stack([T.ttsv_all_but_one(X, A[:, j]) for j in range(r)], axis=1)
+    w = np.sum(A * Y, axis=0)
+    B = A.T @ A
+    C = B ** (d - 1)
+    u = (B * C) @ lam
+    f = alpha + lam @ u - 2.0 * (w @ lam)
+    g_lambda = -2.0 * (w - u)
+    G_A = -2.0 * d * (Y - A @ (lam[:, None] * C)) * lam[None, :]
+    return FG(f, g_lambda, G_A, Y=Y, w=w, u=u, C=C)
+
+
 @dataclass
 class Magnitudes:
     """Sizes of the terms that cancel in f, g_lambda and G_A.
@@ -144,5 +163,27 @@ def magnitudes(V, nu, A, lam, d: int, alpha: float = 0.0) -> Magnitudes:
     f_scale = abs(alpha) + abs(lam @ out.u) + 2.0 * abs(out.w @ lam)
     g_scale = 2.0 * (wabs + uabs)
     ADC = np.abs(A) @ (np.abs(lam)[:, None] * np.abs(out.C))
+    G_scale = 2.0 * d * np.abs(lam) * (Yabs.max(axis=0) + ADC.max(axis=0))
+    return Magnitudes(float(f_scale), g_scale, G_scale)
+
+
+def magnitudes_explicit(X, A, lam, d: int, alpha: float = 0.0) -> Magnitudes:
+    """The scales of Magnitudes for Algorithm 1, whose TTSVs sum the terms
+    X_{i i_2 .. i_d} a_{i_2} .. a_{i_d} of eq. (ExpXbdd): Yabs = |X| |a|^{d-1}
+    and the w terms |X| |a|^d replace their implicit counterparts."""
+    X = np.asarray(X, dtype=np.float64)
+    A = np.asarray(A, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    out = fg_explicit(X, A, lam, d, alpha)
+    Xa = np.abs(X)
+    Aa = np.abs(A)
+    r = A.shape[1]
+    Yabs = np.stack([T.ttsv_all_but_one(Xa, Aa[:, j]) for j in range(r)], axis=1)
+    wabs = np.sum(Aa * Yabs, axis=0)
+    Babs = np.abs(A.T @ A)
+    uabs = Babs ** d @ np.abs(lam)
+    f_scale = abs(alpha) + abs(lam @ out.u) + 2.0 * abs(out.w @ lam)
+    g_scale = 2.0 * (wabs + uabs)
+    ADC = Aa @ (np.abs(lam)[:, None] * np.abs(out.C))
     G_scale = 2.0 * d * np.abs(lam) * (Yabs.max(axis=0) + ADC.max(axis=0))
     return Magnitudes(float(f_scale), g_scale, G_scale)

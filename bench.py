@@ -20,6 +20,8 @@ iterations from a Gaussian start.
 "mid": d=4, n=100, r=20, p=5000, fp64 and fp32: evaluation throughput, and a
 full solve (10 randomized-range-finder restarts) for each sigma in {1e-4,
 1e-3, 1e-2, 1e-1} with its relative error and similarity score.
+"table1": Section 4.1's explicit (stored n^d tensor, Algorithm 1) against
+implicit (Algorithm 2) evaluation at Table 1's scenarios, fp64.
 "stochastic": Section 5's comparison at d=3, n=500, r=10, p=500,000,
 sigma=0.1: L-BFGS on the full data against Adam on s in {10, 100, 1000}
 sampled columns per step, from the same ten starts.
@@ -417,6 +419,54 @@ def stoch_leg(S, ctx, pgtol):
     return out
 
 
+# Table 1's scenarios (d, n, p, r) and the paper's seconds per iteration
+# (explicit, implicit), MATLAB on the CPU it names: context only
+TABLE1 = [(3, 75, 750, 5, 5.30e-04, 4.36e-04), (3, 75, 750, 25, 1.91e-03, 5.91e-04),
+          (3, 75, 3750, 5, 5.17e-04, 7.96e-04), (3, 75, 3750, 25, 1.90e-03, 1.03e-03),
+          (3, 375, 3750, 5, 2.29e-02, 4.82e-03), (4, 75, 3750, 5, 1.47e-02, 9.22e-04)]
+
+
+def table1_leg(S, ctx, reps=50):
+    """Section 4.1: the explicit route (Algorithm 1 on the stored n^d
+    tensor) against the implicit one (Algorithm 2) per evaluation, fp64,
+    V ~ U(0,1), at Table 1's scenarios.  The tensor's formation is timed
+    apart (the paper leaves it out of the comparison)."""
+    import torch
+    rows = []
+    for k, (d, n, p, r, pe, pi) in enumerate(TABLE1):
+        V, nu = synth.uniform_obs(n, p, 15, k)
+        A = synth.gauss_factors(n, r, 15, k, 5)
+        Vd = S.colmajor(torch.from_numpy(V)).cuda()
+        Ad = S.colmajor(torch.from_numpy(A)).cuda()
+        nud = torch.from_numpy(nu).cuda()
+        lam = torch.ones(r, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = S.symtd_form_moment(ctx, Vd, nud, d)
+        torch.cuda.synchronize()
+        t_form = time.perf_counter() - t0
+
+        def rate(fn):
+            out = fn(None)
+            for _ in range(5):
+                fn(out)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                fn(out)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t1) / reps
+
+        t_exp = rate(lambda o: S.symtd_fg_explicit(ctx, X, n, d, Ad, lam, 0.0, out=o))
+        t_imp = rate(lambda o: S.symtd_fg(ctx, Vd, nud, Ad, lam, d, 0.0, out=o))
+        rows.append({"d": d, "n": n, "p": p, "r": r, "explicit_us": 1e6 * t_exp, "implicit_us": 1e6 * t_imp,
+                     "speedup_implicit": t_exp / t_imp, "form_ms": 1e3 * t_form,
+                     "explicit_tensor_MB": 8 * n ** d / 1e6,
+                     "paper_s_per_iter": {"explicit": pe, "implicit": pi}})
+        del X
+    return {"workload": "Table 1 scenarios, V ~ U(0,1), fp64, per evaluation (f, g_lambda, G_A)", "rows": rows}
+
+
 def batched_leg(S, ctx, count, pgtol):
     import torch
     probs, sigma = grouped_problems(count, 4, pgtol)
@@ -703,6 +753,7 @@ def main():
         res["normx"] = normx_leg(S, ctx, V32, nu, d)
         res["small"] = small_leg(S, ctx)
         res["mid"] = mid_leg(S, ctx, args.pgtol)
+        res["table1"] = table1_leg(S, ctx)
         if not args.no_stoch:
             res["stochastic"] = stoch_leg(S, ctx, args.pgtol)
         if args.batched > 0:

@@ -294,6 +294,30 @@ symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb,
                          const symtd_solve_opts* opts, symtd_solve_result* out);
 
 /* ------------------------------------------------------------------------
+ * The explicit route (Algorithm 1, fg_explicit): the data tensor stored as a
+ * dense n^d array, for the comparison of Section 4.1 (Table 1).  X must be
+ * symmetric; entry (i_1, .., i_d) is at i_1 + n i_2 + .. + n^{d-1} i_d.
+ * ------------------------------------------------------------------------ */
+
+/* X = sum_l nu_l v_l^{(x)d} (eq. (tensorX)), every entry summed in fp64
+ * over the observations and stored in the type dt.  X: n^d values (device),
+ * fully overwritten; n^{d-1} < 2^31.  Asynchronous. */
+symtd_status symtd_form_moment(symtd_ctx* ctx, void* stream, symtd_dtype dt,
+                               const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
+                               int d, void* X);
+
+/* Algorithm 1: y_j = X a_j^{d-1} (eq. (ExpXbdd)), w_j = a_j'y_j, and f,
+ * g_lambda, G_A as in symtd_fg (same closing kernel, same precisions:
+ * SYMTD_PREC_FP64 for fp64 storage, SYMTD_PREC_FP32 for fp32).  The first
+ * of the d - 1 contracted modes runs on the matrix cores (the first product
+ * of symtd_fg, with X's mode-1 unfolding as n^{d-1} unit-weight columns),
+ * the others in a second kernel.  O(r n^d) work.  n^{d-1} < 2^31.
+ * Asynchronous; the context's workspace is used. */
+symtd_status symtd_fg_explicit(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* X, int64_t n, int d,
+                               const void* A, int64_t lda, const double* lambda, int64_t r, double alpha,
+                               symtd_prec prec, double* f, double* g_lambda, void* G_A, int64_t ldg);
+
+/* ------------------------------------------------------------------------
  * Stochastic objective and Adam (Section 5).
  *
  * For very many observations, the objective and gradient are estimated from

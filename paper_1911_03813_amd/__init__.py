@@ -135,6 +135,9 @@ SIGNATURES = {
     "symtd_fg_data": (_int, [_vp, _vp, _vp, _vp, _i64, _vp, _i64, _int, _dbl, _vp, _vp, _vp, _i64]),
     "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
     "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
+    "symtd_form_moment": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _vp]),
+    "symtd_fg_explicit": (_int, [_vp, _vp, _int, _vp, _i64, _int, _vp, _i64, _vp, _i64, _dbl, _int, _vp, _vp, _vp,
+                                 _i64]),
     "symtd_fg_sampled": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _i64, _c.c_uint64, _i64, _vp, _i64,
                                 _vp, _i64, _int, _int, _vp, _vp, _vp, _i64, _vp]),
     "symtd_adam_opts_default": (_int, [_c.POINTER(AdamOpts)]),
@@ -418,6 +421,43 @@ def symtd_solve(ctx: Context, V, nu, d: int, r: int, *, prec: int | None = None,
     _check(ctx, lib().symtd_solve(ctx.handle, _stream(stream), ctypes.byref(call.pb), ctypes.byref(call.opts),
                                   ctypes.byref(call.res)))
     return call.result()
+
+
+def symtd_form_moment(ctx: Context, V, nu, d: int, out=None, stream=None):
+    """The dense moment tensor X = sum_l nu_l v_l^{(x)d} as a flat device
+    tensor of n^d entries (entry (i_1, .., i_d) at i_1 + n i_2 + ...)."""
+    import torch
+    Vp, ldv = _mat(V, "V")
+    n, p = V.shape
+    X = out if out is not None else torch.empty(n ** d, dtype=V.dtype, device=V.device)
+    if X.dtype != V.dtype or X.numel() != n ** d or not X.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of n^d entries of V's dtype")
+    _check(ctx, lib().symtd_form_moment(ctx.handle, _stream(stream), _dt(V), Vp, ldv, _vec(nu, "nu", p), n, p,
+                                        int(d), X.data_ptr()))
+    return X
+
+
+def symtd_fg_explicit(ctx: Context, X, n: int, d: int, A, lam, alpha: float = 0.0, prec: int | None = None,
+                      out=None, stream=None):
+    """Algorithm 1 on a dense symmetric tensor X (flat, n^d entries)."""
+    import torch
+    Ap, lda = _mat(A, "A", X.dtype)
+    r = A.shape[1]
+    if A.shape[0] != n or X.numel() != n ** d or not X.is_contiguous() or not X.is_cuda:
+        raise ValueError("X must be a contiguous GPU tensor of n^d entries and A n x r")
+    if prec is None:
+        prec = PREC_FP64 if X.dtype == torch.float64 else PREC_FP32
+    if out is None:
+        f = torch.empty(1, dtype=torch.float64, device=X.device)
+        g = torch.empty(r, dtype=torch.float64, device=X.device)
+        G = colmajor(torch.empty(n, r, dtype=X.dtype, device=X.device))
+    else:
+        f, g, G = out
+    Gp, ldg = _mat(G, "G_A", X.dtype)
+    _check(ctx, lib().symtd_fg_explicit(ctx.handle, _stream(stream), F64 if X.dtype == torch.float64 else F32,
+                                        X.data_ptr(), n, int(d), Ap, lda, _vec(lam, "lambda", r), r, float(alpha),
+                                        int(prec), _vec(f, "f", 1), _vec(g, "g_lambda", r), Gp, ldg))
+    return f, g, G
 
 
 def symtd_fg_sampled(ctx: Context, V, nu, A, lam, d: int, s: int, seed: int, draw: int, prec: int | None = None,

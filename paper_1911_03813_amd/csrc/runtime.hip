@@ -146,25 +146,9 @@ struct Carve {
 template <typename X>
 bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-struct FgPlan {
-  int nt_tot, rp, nblk, nt1, nt2, g1w, nslab, nblocks, nsplit, blk_per_split, rowblocks;
-  int64_t npad;
-  int64_t ldap;
-  size_t apad, wp, wpart, part, ypart, rr, fp;  // element counts
-  size_t bytes(size_t esz) const {
-    size_t s = 0;
-    auto add = [&](size_t b) { s = ((s + 255) & ~(size_t)255) + b; };
-    add(apad * esz);
-    add(wp * esz);
-    add(wpart * sizeof(double));
-    add(part * esz);
-    add(ypart * esz);
-    add(rr * sizeof(double));
-    add(rr * sizeof(double));
-    add(fp * sizeof(double));
-    return s + 256;
-  }
-};
+}  // namespace
+
+namespace symtd {
 
 FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_blocks, int64_t g2_splits) {
   FgPlan P;
@@ -198,9 +182,6 @@ FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_bl
   return P;
 }
 
-}  // namespace
-
-namespace symtd {
 
 template <typename T>
 symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu,

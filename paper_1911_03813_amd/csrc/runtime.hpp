@@ -65,6 +65,30 @@ struct symtd_ctx {
 
 namespace symtd {
 
+// Launch shape and workspace of one evaluation (the products' splits and the
+// element counts of the workspace buffers), from the sizes alone.
+struct FgPlan {
+  int nt_tot, rp, nblk, nt1, nt2, g1w, nslab, nblocks, nsplit, blk_per_split, rowblocks;
+  int64_t npad;
+  int64_t ldap;
+  size_t apad, wp, wpart, part, ypart, rr, fp;  // element counts
+  size_t bytes(size_t esz) const {
+    size_t s = 0;
+    auto add = [&](size_t b) { s = ((s + 255) & ~(size_t)255) + b; };
+    add(apad * esz);
+    add(wp * esz);
+    add(wpart * sizeof(double));
+    add(part * esz);
+    add(ypart * esz);
+    add(rr * sizeof(double));
+    add(rr * sizeof(double));
+    add(fp * sizeof(double));
+    return s + 256;
+  }
+};
+
+FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_blocks, int64_t g2_splits);
+
 // Algorithm 2 for `ng` models of r columns side by side (model m = columns
 // m r .. m r + r - 1 of A, lambda, g_lambda, G_A; f holds ng values).
 // Arguments are checked by the caller.

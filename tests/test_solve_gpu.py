@@ -175,6 +175,13 @@ def test_noiseless_mixture_recovers_means(ctx):
     A = out["A"].cpu().numpy()
     assert out["rel_err"] < 1e-5
     assert score(A, mu) > 0.999
+    # the oracle's solve from the same starts (eq. (rrf), Philox draws) ends
+    # at the same score, and the library's score of eq. (Score) agrees with
+    # the oracle's
+    alpha = normx_implicit(V, nu, d)
+    ref = solve(V, nu, d, r, alpha=alpha, restarts=3, init=INIT_RRF, seed=1, pgtol=1e-10, ftol=0.0, max_iters=3000)
+    assert abs(score(ref.A, mu) - score(A, mu)) <= 1e-6
+    assert abs(S.metrics.similarity_score(mu, A) - score(A, mu)) <= 1e-14
 
 
 def test_exit_codes(ctx):

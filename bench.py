@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--batched", type=int, default=512, help="problems of the batched leg")
     ap.add_argument("--served", type=int, default=600, help="requests of the served leg")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the served leg (requests/s)")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_1911_03813_amd", "tuning", "mi355x.json"),
+                    help="tuning table (JSON cache written by paper_1911_03813_amd.autotune) to load first")
+    ap.add_argument("--no-tuning", action="store_true", help="run with the built-in launch shapes")
     ap.add_argument("--study", action="store_true",
                     help="only run the Section 4.2 studies (mean recovery over ranks, RRF against random starts)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -702,6 +705,12 @@ def main():
 
     import paper_1911_03813_amd as S
 
+    from paper_1911_03813_amd import autotune
+    autotune.clear()
+    tuning = {"cache": None, "entries": 0}
+    if not args.no_tuning and os.path.exists(args.tuning):
+        tuning = {"cache": os.path.relpath(args.tuning, ROOT), "entries": autotune.load(args.tuning)}
+
     W = WORKLOAD
     d, n, r, p = W["d"], W["n"], W["r"], W["p"]
     lowp = args.prec in ("fp16", "bf16x3")
@@ -819,6 +828,7 @@ def main():
         "kernels_us_per_step_note": f"every kernel, timed over {bsteps} steps after the timed region",
         "per_call": calls,
         "graph_replay": graph,
+        "tuning": tuning,
     }
     if data is not None:
         data.close()

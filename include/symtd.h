@@ -483,8 +483,59 @@ void symtd_server_result_release(symtd_server_result* res);
 void symtd_server_destroy(symtd_server* srv);
 
 /*
+ * The tuning table and the autotuners.  The table is process-wide and holds,
+ * per (kind, precision, ceil(log2 n), ceil(log2 p), ceil(log2 r)) bucket, the
+ * launch shape an autotuner measured fastest:
+ *   SYMTD_TUNE_KIND_FG       v0 = blocks sharing the first product, v1 =
+ *                            splits of the observations in the second
+ *                            product, for symtd_fg and everything built on
+ *                            it (r = all evaluated columns, restarts
+ *                            included); SYMTD_TUNE_G1_BLOCKS / G2_SPLITS set
+ *                            on a context take precedence
+ *   SYMTD_TUNE_KIND_GROUPED  v0 = 16-observation blocks per split of the
+ *                            grouped second product (batched solve, server),
+ *                            r = an instance's columns (restarts included)
+ * Evaluations read the table when they are planned: with a fixed table, an
+ * instance's launch shape, summation order and result bits depend only on
+ * its own sizes.  Changing the table while other threads evaluate is
+ * allowed, but their shapes may then change between calls.
+ */
+typedef enum symtd_tune_kind { SYMTD_TUNE_KIND_FG = 0, SYMTD_TUNE_KIND_GROUPED = 1 } symtd_tune_kind;
+typedef struct symtd_tune_entry {
+  int kind;                 /* symtd_tune_kind */
+  int prec;                 /* symtd_prec: SYMTD_PREC_FP64 or SYMTD_PREC_FP32 */
+  int n_bucket, p_bucket, r_bucket;   /* ceil(log2 x) of n, p, r */
+  int64_t v0, v1;           /* the launch shape (see above), >= 0 */
+  double us;                /* measured time of one evaluation (informational) */
+} symtd_tune_entry;
+/* Insert an entry, replacing one with the same key. */
+symtd_status symtd_tune_put(const symtd_tune_entry* e);
+int64_t symtd_tune_count(void);
+symtd_status symtd_tune_get(int64_t index, symtd_tune_entry* e);
+void symtd_tune_clear(void);
+
+/* Time symtd_fg on the given data for first-product blocks in {1/4, 1/2,
+ * 3/4, 1} x compute units and second-product splits in {1/2, 1, 2, 4} x the
+ * automatic count (median of three rounds of `reps` calls, after two
+ * warm-up calls), put the fastest into the table and return it in *out (may
+ * be NULL).  Arguments as in symtd_fg. */
+symtd_status symtd_autotune_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
+                               const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
+                               const double* lambda, int64_t r, int d, symtd_prec prec, int reps,
+                               symtd_tune_entry* out);
+
+/* Time the grouped evaluation (symtd_fg_batched) of `copies` instances of
+ * shape (n, p, d) with `cols` columns each (factors taken from V's first
+ * columns) for second-product splits of 4, 8, 16, 32 and 64 blocks of 16
+ * observations, put the fastest into the table and return it.  Allocates
+ * its own buffers. */
+symtd_status symtd_autotune_grouped(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
+                                    const double* nu, int64_t n, int64_t p, int d, int64_t cols, int copies,
+                                    int reps, symtd_tune_entry* out);
+
+/*
  * Work-split tuning of the evaluation kernels (tests force particular splits
- * with it). Keys:
+ * with it; the autotuners use it). Keys:
  *   SYMTD_TUNE_G1_BLOCKS  blocks sharing the first product V'A (0 = automatic:
  *                         one per compute unit, never more than the number of
  *                         observation slabs; larger requests are clamped)

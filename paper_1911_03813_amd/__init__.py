@@ -100,6 +100,13 @@ class AdamOpts(ctypes.Structure):
                 ("init", ctypes.c_int), ("A0", ctypes.c_void_p)]
 
 
+class TuneEntry(ctypes.Structure):
+    """symtd_tune_entry"""
+    _fields_ = [("kind", ctypes.c_int), ("prec", ctypes.c_int), ("n_bucket", ctypes.c_int),
+                ("p_bucket", ctypes.c_int), ("r_bucket", ctypes.c_int), ("v0", ctypes.c_int64),
+                ("v1", ctypes.c_int64), ("us", ctypes.c_double)]
+
+
 class SolveResult(ctypes.Structure):
     """symtd_solve_result"""
     _fields_ = [("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("lam", ctypes.c_void_p),
@@ -153,6 +160,14 @@ SIGNATURES = {
     "symtd_server_destroy": (None, [_vp]),
     "symtd_solve_batched": (_int, [_vp, _vp, _i64, _c.POINTER(Problem), _c.POINTER(SolveOpts),
                                    _c.POINTER(SolveResult)]),
+    "symtd_tune_put": (_int, [_c.POINTER(TuneEntry)]),
+    "symtd_tune_count": (_i64, []),
+    "symtd_tune_get": (_int, [_i64, _c.POINTER(TuneEntry)]),
+    "symtd_tune_clear": (None, []),
+    "symtd_autotune_fg": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int, _int, _int,
+                                 _c.POINTER(TuneEntry)]),
+    "symtd_autotune_grouped": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _i64, _int, _int,
+                                      _c.POINTER(TuneEntry)]),
     "symtd_profile_enable": (_int, [_vp, ctypes.c_uint32]),
     "symtd_profile_reset": (_int, [_vp]),
     "symtd_profile_read": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),

@@ -36,7 +36,8 @@ symtd_status run_fg_batched(symtd_ctx* ctx, hipStream_t st, int64_t count, const
       G.alpha = it.alpha;
       const int64_t nblk = (p + 15) / 16;
       G.ntile = (int)((p + GG1_TILE - 1) / GG1_TILE);
-      G.nsplit = (int)((nblk + GG2_SPLIT_BLK - 1) / GG2_SPLIT_BLK);
+      G.split_blk = grouped_split_blocks(sizeof(T) == 8, n, p, cols);
+      G.nsplit = (int)((nblk + G.split_blk - 1) / G.split_blk);
       G.ldy = 64 * ((n + 63) / 64);
       G.Wp = cv.take<T>((size_t)nblk * G.nt * 256);
       G.wpart = cv.take<double>((size_t)G.ntile * cols);

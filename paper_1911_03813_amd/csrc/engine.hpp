@@ -121,7 +121,8 @@ struct EngineInst {
     const int nt = (int)((cols + 15) / 16);
     const int64_t nblk = (p + 15) / 16;
     const int ntile = (int)((p + GG1_TILE - 1) / GG1_TILE);
-    const int nsplit = (int)((nblk + GG2_SPLIT_BLK - 1) / GG2_SPLIT_BLK);
+    const int split_blk = grouped_split_blocks(sizeof(T) == 8, n, p, cols);
+    const int nsplit = (int)((nblk + split_blk - 1) / split_blk);
     const int64_t ldy = 64 * ((n + 63) / 64);
     const int m = o.m;
     Carver c(base);
@@ -152,7 +153,7 @@ struct EngineInst {
     bytes = c.off + 256;
     g.ldv = ld; g.lda = ld; g.ldg = ld;
     g.n = (int)n; g.p = (int)p; g.d = pb.d; g.r = (int)r; g.R = R; g.cols = (int)cols; g.nt = nt;
-    g.ntile = ntile; g.nsplit = nsplit; g.ldy = ldy;
+    g.ntile = ntile; g.nsplit = nsplit; g.ldy = ldy; g.split_blk = split_blk;
     if (!base) return;
     lanes.resize(R);
     for (int k = 0; k < R; ++k) {

@@ -22,7 +22,7 @@
 namespace symtd {
 
 constexpr int GG1_TILE = 256;        // observations per ggemm1 item (4 waves x 4 blocks of 16)
-constexpr int GG2_SPLIT_BLK = 16;    // 16-observation blocks per ggemm2 split (256 observations)
+constexpr int GG2_SPLIT_BLK = 16;    // default 16-observation blocks per ggemm2 split (256 observations)
 constexpr int GG_NT_F32 = 4;         // column subtiles per item (fp32): few enough registers for three waves per SIMD
 constexpr int GG_NT_F64 = 4;         // column subtiles per item (fp64)
 constexpr int GG_NT_MAX = GG_NT_F32 > GG_NT_F64 ? GG_NT_F32 : GG_NT_F64;
@@ -38,6 +38,7 @@ struct GInst {
   T* Wp;                             // packed W, ceil(p/16) x nt x 256
   double* wpart; int ntile;          // [ntile][cols], ntile = ceil(p / GG1_TILE)
   T* Ypart; int nsplit; int64_t ldy; // [nsplit][nt*16][ldy], ldy = 64 ceil(n / 64)
+  int split_blk;                     // 16-observation blocks per ggemm2 split (GG2_SPLIT_BLK or tuned)
   double* B; double* C;              // R blocks of r x r
   double* YM;                        // n x cols, leading dimension n
 };

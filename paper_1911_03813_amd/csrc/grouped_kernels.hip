@@ -157,8 +157,8 @@ __device__ void ggemm2_body(const GInst<T>& I, int rb, int split, int cg) {
   const int64_t il = ibase + 4 * c;
   const int64_t n4 = (n + 3) & ~(int64_t)3;
   const int64_t nblk = (p + 15) / 16;
-  const int64_t b0 = (int64_t)split * GG2_SPLIT_BLK;
-  const int64_t b1 = min(nblk, b0 + GG2_SPLIT_BLK);
+  const int64_t b0 = (int64_t)split * I.split_blk;
+  const int64_t b1 = min(nblk, b0 + (int64_t)I.split_blk);
   acc_t acc[4][NT];
 #pragma unroll
   for (int m = 0; m < 4; ++m)

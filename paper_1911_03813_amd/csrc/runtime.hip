@@ -191,7 +191,15 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
   const bool f64 = sizeof(T) == 8;
   const int64_t r1 = r;            // columns of one model
   r = r1 * ng;                     // columns of all models (the products see them all)
-  FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count, ctx->tune_g1_blocks, ctx->tune_g2_splits);
+  int64_t g1 = ctx->tune_g1_blocks, g2 = ctx->tune_g2_splits;
+  if (g1 == 0 || g2 == 0) {
+    int64_t t1 = 0, t2 = 0;
+    if (tuned_fg(f64, n, p, r, &t1, &t2)) {
+      if (g1 == 0) g1 = t1;
+      if (g2 == 0) g2 = t2;
+    }
+  }
+  FgPlan P = plan_fg(n, p, r, f64, ctx->cu_count, g1, g2);
   P.rr = (size_t)ng * r1 * r1;      // B and C: one r1 x r1 block per model
   if (P.nblocks > ctx->nflags) return ctx->fail(SYMTD_EINVAL, "internal: %d blocks exceed the flag array", P.nblocks);
   const size_t need = P.bytes(sizeof(T));

@@ -89,6 +89,14 @@ struct FgPlan {
 
 FgPlan plan_fg(int64_t n, int64_t p, int64_t r, bool f64, int cus, int64_t g1_blocks, int64_t g2_splits);
 
+// The tuning table (symtd_tune_*, process-wide): the first-product blocks
+// and second-product splits of an evaluation, and the split length of the
+// grouped second product, by (precision, log2 buckets of n, p and the
+// evaluated columns).  Lookups return false / the default when no entry
+// matches; a result depends only on the shape and the table.
+bool tuned_fg(bool f64, int64_t n, int64_t p, int64_t cols, int64_t* g1_blocks, int64_t* g2_splits);
+int grouped_split_blocks(bool f64, int64_t n, int64_t p, int64_t cols);
+
 // Algorithm 2 for `ng` models of r columns side by side (model m = columns
 // m r .. m r + r - 1 of A, lambda, g_lambda, G_A; f holds ng values).
 // Arguments are checked by the caller.

@@ -26,6 +26,9 @@ Anal. Appl., 2020; arXiv 1911.03813):
   the device.
 * ``stochastic`` - the sampled objective of Section 5 (Lemma 5.1) and Adam
   with the paper's epoch, learning-rate and restore schedule.
+* ``corrected`` - moments corrected for spherical Gaussian noise (the
+  lower-order terms of Section 4.2, left as future work in Section 6),
+  derived from Isserlis' theorem for d = 3 and d = 4.
 
 Pins (tests marked "not gpu") tie every function to something other than
 itself: brute force on explicit tensors, closed forms, invariants and

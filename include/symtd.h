@@ -260,6 +260,11 @@ typedef struct symtd_solve_opts {
   const void* A0;           /* optional device starts, n x (restarts r) of type dt, leading
                                dimension n (restart k = columns k r ..); NULL = draw them */
   int check_every;          /* evaluation steps between polls of the stop flags (0 = automatic) */
+  double sigma;             /* > 0: minimise the objective of the moment corrected for spherical
+                               Gaussian noise of this level, ||X - Delta - M||^2 (d = 3 or 4,
+                               n <= 4096; see symtd_fg_corrected); alpha then stands for
+                               ||X - Delta||^2 (computed, given or 0).  0 = the plain objective.
+                               symtd_solve only (the batched and served forms refuse it) */
 } symtd_solve_opts;
 
 typedef struct symtd_solve_result {
@@ -287,11 +292,50 @@ typedef struct symtd_solve_result {
 
 /* Fill `opts` with defaults: fp32 products, m = 5, pgtol = 1e-4, ftol =
  * 2.22e-9, max_iters = 10000, max_evals = 50000 (Section 4), 1 restart,
- * seed 0, RRF starts, alpha computed. */
+ * seed 0, RRF starts, alpha computed, no noise correction. */
 symtd_status symtd_solve_opts_default(symtd_solve_opts* opts);
 
 symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb,
                          const symtd_solve_opts* opts, symtd_solve_result* out);
+
+/* ------------------------------------------------------------------------
+ * Moments corrected for spherical Gaussian noise (the lower-order terms that
+ * keep X from being exactly of rank r, Section 4.2; the paper leaves their
+ * removal to future work).  For v = mu + sigma g with g ~ N(0, I), Isserlis'
+ * theorem gives E[v^{(x)d}] = E[mu^{(x)d}] + Delta with
+ *   d = 3:  Delta = sigma^2 sym3(m (x) I)
+ *   d = 4:  Delta = sigma^2 sym6(S (x) I) + sigma^4 sym3(I (x) I)
+ * where m = sum_l nu_l v_l, S = sum_l nu_l v_l v_l' - sigma^2 I and symK sums
+ * the K placements of the factors over the d index positions.  The corrected
+ * objective ||X - Delta - M||^2 = f + 2 sum_j lambda_j Delta a_j^d + constant.
+ * ------------------------------------------------------------------------ */
+
+/* m = sum_l nu_l v_l (n fp64 values) and, when M2 is not NULL, M2 = sum_l
+ * nu_l v_l v_l' (n x n fp64, column-major), device pointers, summed in fp64.
+ * Asynchronous. */
+symtd_status symtd_moment_stats(symtd_ctx* ctx, void* stream, symtd_dtype dt,
+                                const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
+                                double* m, double* M2);
+
+/* symtd_fg, then the correction of the noise level sigma >= 0 (d = 3 or 4,
+ * n <= 4096; m and, for d = 4, M2 from symtd_moment_stats):
+ *   f += 2 sum_j lambda_j Delta a_j^d, g_lambda_j += 2 Delta a_j^d,
+ *   column j of G_A += 2 d lambda_j Delta a_j^{d-1},
+ * so that with alpha = alpha_c (symtd_alpha_corrected) f = ||X - Delta - M||^2.
+ * The correction terms are formed in fp64.  Asynchronous. */
+symtd_status symtd_fg_corrected(symtd_ctx* ctx, void* stream, symtd_dtype dt,
+                                const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
+                                const void* A, int64_t lda, const double* lambda, int64_t r, int d,
+                                double alpha, symtd_prec prec, double sigma, const double* m, const double* M2,
+                                double* f, double* g_lambda, void* G_A, int64_t ldg);
+
+/* alpha_c = ||X - Delta||^2 = alpha - 2 <X, Delta> + ||Delta||^2 for alpha =
+ * ||X||^2 (symtd_normX): <X, Delta> = sum_l nu_l Delta v_l^d on the device,
+ * ||Delta||^2 in closed form.  *alpha_c is a HOST value; synchronous. */
+symtd_status symtd_alpha_corrected(symtd_ctx* ctx, void* stream, symtd_dtype dt,
+                                   const void* V, int64_t ldv, const double* nu, int64_t n, int64_t p,
+                                   int d, double sigma, const double* m, const double* M2, double alpha,
+                                   double* alpha_c);
 
 /* ------------------------------------------------------------------------
  * The explicit route (Algorithm 1, fg_explicit): the data tensor stored as a

@@ -56,7 +56,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("m", ctypes.c_int), ("pgtol", ctypes.c_double), ("ftol", ctypes.c_double),
                 ("max_iters", ctypes.c_int64), ("max_evals", ctypes.c_int64), ("restarts", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("init", ctypes.c_int), ("alpha_mode", ctypes.c_int),
-                ("alpha", ctypes.c_double), ("A0", ctypes.c_void_p), ("check_every", ctypes.c_int)]
+                ("alpha", ctypes.c_double), ("A0", ctypes.c_void_p), ("check_every", ctypes.c_int),
+                ("sigma", ctypes.c_double)]
 
 
 class FgItem(ctypes.Structure):
@@ -143,6 +144,11 @@ SIGNATURES = {
     "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
     "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
     "symtd_form_moment": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _vp]),
+    "symtd_moment_stats": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _vp]),
+    "symtd_fg_corrected": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int, _dbl,
+                                  _int, _dbl, _vp, _vp, _vp, _vp, _vp, _i64]),
+    "symtd_alpha_corrected": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _dbl, _vp, _vp, _dbl,
+                                     _c.POINTER(_dbl)]),
     "symtd_fg_explicit": (_int, [_vp, _vp, _int, _vp, _i64, _int, _vp, _i64, _vp, _i64, _dbl, _int, _vp, _vp, _vp,
                                  _i64]),
     "symtd_fg_sampled": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _i64, _c.c_uint64, _i64, _vp, _i64,
@@ -363,7 +369,7 @@ class _SolveCall:
 
     def __init__(self, V, nu, d, r, prec=None, m=5, pgtol=1e-4, ftol=2.220446049250313e-09, max_iters=10000,
                  max_evals=50000, restarts=1, seed=0, init=None, alpha=None, A0=None, check_every=0,
-                 trace_len=0):
+                 trace_len=0, sigma=0.0):
         import numpy as np
         import torch
         Vp, ldv = _mat(V, "V")
@@ -391,6 +397,7 @@ class _SolveCall:
             o.A0 = A0p
             self.keep.append(A0)
         o.check_every = int(check_every)
+        o.sigma = float(sigma)
         self.opts = o
         self.A = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
         self.lam = torch.empty(r, dtype=torch.float64, device=V.device)
@@ -423,19 +430,86 @@ class _SolveCall:
 def symtd_solve(ctx: Context, V, nu, d: int, r: int, *, prec: int | None = None, m: int = 5, pgtol: float = 1e-4,
                 ftol: float = 2.220446049250313e-09, max_iters: int = 10000, max_evals: int = 50000,
                 restarts: int = 1, seed: int = 0, init: int = INIT_RRF, alpha=None, A0=None,
-                check_every: int = 0, trace_len: int = 0, stream=None):
+                check_every: int = 0, trace_len: int = 0, sigma: float = 0.0, stream=None):
     """Restarted L-BFGS solve on the device (symtd_solve).
 
     alpha: None = compute ||X||^2 on the device, a positive number = use it,
     0 = shifted objective.  A0 (optional): n x (restarts*r) column-major
-    device tensor of starts.  Returns a dict with the best model (A, lam as
+    device tensor of starts.  sigma > 0 (d = 3 or 4): fit the moment
+    corrected for spherical Gaussian noise of that level; alpha then stands
+    for ||X - Delta||^2.  Returns a dict with the best model (A, lam as
     device tensors) and the host figures of the solve.
     """
     call = _SolveCall(V, nu, d, r, prec, m, pgtol, ftol, max_iters, max_evals, restarts, seed, init, alpha, A0,
-                      check_every, trace_len)
+                      check_every, trace_len, sigma)
     _check(ctx, lib().symtd_solve(ctx.handle, _stream(stream), ctypes.byref(call.pb), ctypes.byref(call.opts),
                                   ctypes.byref(call.res)))
     return call.result()
+
+
+def symtd_moment_stats(ctx: Context, V, nu, second: bool = True, stream=None):
+    """m = sum_l nu_l v_l (n,) and, when `second`, M2 = sum_l nu_l v_l v_l'
+    (n x n, column-major), fp64 device tensors."""
+    import torch
+    Vp, ldv = _mat(V, "V")
+    n, p = V.shape
+    m = torch.empty(n, dtype=torch.float64, device=V.device)
+    M2 = colmajor(torch.empty(n, n, dtype=torch.float64, device=V.device)) if second else None
+    _check(ctx, lib().symtd_moment_stats(ctx.handle, _stream(stream), _dt(V), Vp, ldv, _vec(nu, "nu", p), n, p,
+                                         m.data_ptr(), M2.data_ptr() if second else None))
+    return m, M2
+
+
+def _m2(M2, n):
+    """Device pointer of an n x n fp64 M2 stored densely (either order: M2 is symmetric)."""
+    import torch
+    if M2 is None:
+        return None
+    if not isinstance(M2, torch.Tensor) or tuple(M2.shape) != (n, n) or M2.dtype != torch.float64 or not M2.is_cuda:
+        raise TypeError("M2 must be an n x n float64 GPU tensor")
+    if not (M2.is_contiguous() or M2.t().is_contiguous()):
+        raise ValueError("M2 must be stored densely")
+    return M2.data_ptr()
+
+
+def symtd_fg_corrected(ctx: Context, V, nu, A, lam, d: int, sigma: float, m, M2=None, alpha: float = 0.0,
+                       prec: int | None = None, out=None, stream=None):
+    """symtd_fg plus the correction for spherical Gaussian noise of level
+    sigma (m, M2 from symtd_moment_stats; M2 needed for d = 4)."""
+    import torch
+    Vp, ldv = _mat(V, "V")
+    Ap, lda = _mat(A, "A", V.dtype)
+    n, p = V.shape
+    if A.shape[0] != n:
+        raise ValueError("A must have as many rows as V")
+    r = A.shape[1]
+    if prec is None:
+        prec = PREC_FP64 if V.dtype == torch.float64 else PREC_FP32
+    if out is None:
+        f = torch.empty(1, dtype=torch.float64, device=V.device)
+        g = torch.empty(r, dtype=torch.float64, device=V.device)
+        G = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
+    else:
+        f, g, G = out
+    Gp, ldg = _mat(G, "G_A", V.dtype)
+    M2p = _m2(M2, n)
+    _check(ctx, lib().symtd_fg_corrected(ctx.handle, _stream(stream), _dt(V), Vp, ldv, _vec(nu, "nu", p), n, p,
+                                         Ap, lda, _vec(lam, "lambda", r), r, int(d), float(alpha), int(prec),
+                                         float(sigma), _vec(m, "m", n), M2p, _vec(f, "f", 1),
+                                         _vec(g, "g_lambda", r), Gp, ldg))
+    return f, g, G
+
+
+def symtd_alpha_corrected(ctx: Context, V, nu, d: int, sigma: float, m, M2, alpha: float, stream=None) -> float:
+    """||X - Delta||^2 from alpha = ||X||^2 (a host float; synchronous)."""
+    Vp, ldv = _mat(V, "V")
+    n, p = V.shape
+    out = ctypes.c_double(0.0)
+    M2p = _m2(M2, n)
+    _check(ctx, lib().symtd_alpha_corrected(ctx.handle, _stream(stream), _dt(V), Vp, ldv, _vec(nu, "nu", p), n, p,
+                                            int(d), float(sigma), _vec(m, "m", n), M2p, float(alpha),
+                                            ctypes.byref(out)))
+    return out.value
 
 
 def symtd_form_moment(ctx: Context, V, nu, d: int, out=None, stream=None):

@@ -172,6 +172,8 @@ symtd_status symtd_solve_batched(symtd_ctx* ctx, void* stream, int64_t count, co
   for (int64_t i = 0; i < count; ++i) {
     symtd_status s = check_solve(ctx, &pbs[i], &opts[i], &outs[i]);
     if (s != SYMTD_OK) return ctx->fail(s, "problem %lld: %s", (long long)i, ctx->err.c_str());
+    if (opts[i].sigma != 0.0)
+      return ctx->fail(SYMTD_EINVAL, "problem %lld: the noise correction is symtd_solve's only", (long long)i);
     if (pbs[i].dt != pbs[0].dt) return ctx->fail(SYMTD_EINVAL, "problem %lld: all problems must share a dtype", (long long)i);
   }
   if (count == 0) return SYMTD_OK;

@@ -128,9 +128,9 @@ symtd_status symtd_form_moment(symtd_ctx* ctx, void* stream, symtd_dtype dt, con
   if ((s = ctx->set_device()) != SYMTD_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if (dt == SYMTD_F64)
-    launch_moment<double>(st, MomentArgs<double>{(const double*)V, ldv, nu, (int)n, p, d, cols, (double*)X});
+    launch_moment<double>(st, MomentArgs<double>{(const double*)V, ldv, nu, (int)n, p, d, cols, (double*)X, nullptr});
   else
-    launch_moment<float>(st, MomentArgs<float>{(const float*)V, ldv, nu, (int)n, p, d, cols, (float*)X});
+    launch_moment<float>(st, MomentArgs<float>{(const float*)V, ldv, nu, (int)n, p, d, cols, (float*)X, nullptr});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ctx->hip_fail(e, "kernel launch (moment)");
   return SYMTD_OK;

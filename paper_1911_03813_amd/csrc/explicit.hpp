@@ -22,7 +22,8 @@ template <typename T>
 struct MomentArgs {
   const T* V; int64_t ldv; const double* nu; int n; int64_t p; int d;
   int64_t cols;            // n^{d-1}
-  T* X;
+  T* X;                    // the tensor in the storage type, or
+  double* X64;             // (when not null) in fp64
 };
 template <typename T>
 void launch_moment(hipStream_t st, const MomentArgs<T>& a);

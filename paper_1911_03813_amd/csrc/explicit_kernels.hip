@@ -64,7 +64,10 @@ __global__ __launch_bounds__(256) void k_moment(MomentArgs<T> a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t i = i0 + 4 * ty + u, c = c0 + 4 * tx + v;
-      if (i < a.n && c < a.cols) a.X[c * a.n + i] = (T)acc[u][v];
+      if (i < a.n && c < a.cols) {
+        if (a.X64) a.X64[c * a.n + i] = acc[u][v];
+        else a.X[c * a.n + i] = (T)acc[u][v];
+      }
     }
 }
 

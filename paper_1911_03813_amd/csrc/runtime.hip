@@ -11,6 +11,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "corrected.hpp"
 #include "kernels.hpp"
 #include "model_dev.hpp"
 #include "lbfgs.hpp"
@@ -321,18 +322,19 @@ template symtd_status run_rrf<double>(symtd_ctx*, hipStream_t, const double*, in
 template <typename T>
 symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
                         int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d, double alpha,
-                        double* f_out) {
-  // scratch: [V64 n x p][A64 n x r][G64 n x r][g r][f 1]
-  auto plan = [&](Carve& c, double** V64, double** A64, double** G64, double** g, double** f) {
+                        double* f_out, const Correction* corr) {
+  // scratch: [V64 n x p][A64 n x r][G64 n x r][g r][f 1][correction terms r]
+  auto plan = [&](Carve& c, double** V64, double** A64, double** G64, double** g, double** f, double** lc) {
     *V64 = std::is_same<T, float>::value ? c.take<double>((size_t)n * p) : nullptr;
     *A64 = std::is_same<T, float>::value ? c.take<double>((size_t)n * r) : nullptr;
     *G64 = c.take<double>((size_t)n * r);
     *g = c.take<double>((size_t)r);
     *f = c.take<double>(1);
+    *lc = c.take<double>((size_t)r);
   };
-  double *V64, *A64, *G64, *g, *fd;
+  double *V64, *A64, *G64, *g, *fd, *lc;
   Carve probe((void*)256);
-  plan(probe, &V64, &A64, &G64, &g, &fd);
+  plan(probe, &V64, &A64, &G64, &g, &fd, &lc);
   const size_t need = probe.off + 512;
   hipError_t e;
   if (need > ctx->wide_bytes) {
@@ -347,14 +349,16 @@ symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv,
     ctx->wide_bytes = need;
   }
   Carve c(ctx->wide);
-  plan(c, &V64, &A64, &G64, &g, &fd);
+  plan(c, &V64, &A64, &G64, &g, &fd, &lc);
   symtd_status s;
   if constexpr (std::is_same<T, float>::value) {
     launch_widen(st, V, ldv, V64, n, n, p);
     launch_widen(st, A, lda, A64, n, n, r);
     s = run_fg<double>(ctx, st, V64, n, nu, n, p, A64, n, lambda, r, 1, d, alpha, fd, g, G64, n);
+    if (s == SYMTD_OK && corr) launch_correction<double>(st, *corr, A64, n, (int)n, (int)r, 1, lambda, fd, g, G64, n, lc);
   } else {
     s = run_fg<double>(ctx, st, V, ldv, nu, n, p, A, lda, lambda, r, 1, d, alpha, fd, g, G64, n);
+    if (s == SYMTD_OK && corr) launch_correction<double>(st, *corr, A, lda, (int)n, (int)r, 1, lambda, fd, g, G64, n, lc);
   }
   if (s != SYMTD_OK) return s;
   if ((e = hipMemcpyAsync(&ctx->fwide_host, fd, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
@@ -365,9 +369,11 @@ symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv,
 }
 
 template symtd_status final_fp64<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t, int64_t,
-                                        const float*, int64_t, const double*, int64_t, int, double, double*);
+                                        const float*, int64_t, const double*, int64_t, int, double, double*,
+                                        const Correction*);
 template symtd_status final_fp64<double>(symtd_ctx*, hipStream_t, const double*, int64_t, const double*, int64_t,
-                                         int64_t, const double*, int64_t, const double*, int64_t, int, double, double*);
+                                         int64_t, const double*, int64_t, const double*, int64_t, int, double, double*,
+                                         const Correction*);
 
 template <typename S>
 symtd_status run_normx(symtd_ctx* ctx, hipStream_t st, const S* V, int64_t ldv, const double* nu,

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "corrected.hpp"
 #include "kernels.hpp"
 #include "symtd.h"
 
@@ -123,7 +124,17 @@ symtd_status run_rrf(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, in
 template <typename T>
 symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
                         int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d, double alpha,
-                        double* f_out);
+                        double* f_out, const Correction* corr = nullptr);
+
+// noise correction (corrected.hpp): the data's statistics m (and M2, when
+// not null) in fp64, and alpha_c = ||X - Delta||^2 from alpha = ||X||^2
+// (synchronous; scratch holds ceil(p / 256) + 1 values)
+template <typename T>
+void launch_stats(hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n, int64_t p, double* m,
+                  double* M2);
+template <typename T>
+symtd_status corrected_alpha(symtd_ctx* ctx, hipStream_t st, const Correction& c, const T* V, int64_t ldv,
+                             const double* nu, int64_t n, int64_t p, double alpha, double* out, double* scratch);
 
 // argument checks of a solve request (problem, options, result buffers)
 symtd_status check_solve(symtd_ctx* ctx, const symtd_problem* pb, const symtd_solve_opts* o,

@@ -92,6 +92,7 @@ class Server final : public symtd_server {
     if (!pb || !o || !id) return fail(SYMTD_EINVAL, "null problem, options or id");
     if (pb->dt != opts_.dt || o->prec != opts_.prec) return fail(SYMTD_EINVAL, "request dtype/precision differ from the server's");
     if (o->A0) return fail(SYMTD_EINVAL, "served requests draw their own starts (A0 must be NULL)");
+    if (o->sigma != 0.0) return fail(SYMTD_EINVAL, "the noise correction is symtd_solve's only (sigma must be 0)");
     symtd_solve_result dummy{};
     dummy.A = (void*)16; dummy.lambda = (double*)16; dummy.lda = pb->n;
     {

@@ -13,6 +13,7 @@
 
 #include "kernels.hpp"
 #include "lbfgs.hpp"
+#include "corrected.hpp"
 #include "runtime.hpp"
 
 using namespace symtd;
@@ -35,6 +36,9 @@ struct Take {
 template <typename T>
 struct SolveLayout {
   double *x, *g, *dd, *S, *Y, *part, *lam_t, *f_t, *glam_t, *trace, *alpha;
+  double *cm, *cM2, *clc, *cxd;   // noise correction: m, M2, terms per column, <X, Delta> partials
+  bool corr = false, d4 = false;
+  int64_t p = 0;
   T *A_t, *G_t;
   LbLane<T>* lanes;
   LbState* states;
@@ -59,6 +63,10 @@ struct SolveLayout {
     lanes = t.take<LbLane<T>>((size_t)R);
     states = t.take<LbState>((size_t)R);
     done = t.take<int>(1);
+    cm = t.take<double>((size_t)(corr ? n : 0));
+    cM2 = t.take<double>((size_t)(corr && d4 ? n * n : 0));
+    clc = t.take<double>((size_t)(corr ? R * r : 0));
+    cxd = t.take<double>((size_t)(corr ? (p + 255) / 256 + 1 : 0));
     bytes = t.off + 256;
   }
 };
@@ -92,6 +100,9 @@ symtd_status check_solve(symtd_ctx* ctx, const symtd_problem* pb, const symtd_so
   symtd_status s = ctx->check_common(pb->dt, pb->V, pb->ldv, pb->nu, pb->n, pb->p, pb->d);
   if (s != SYMTD_OK) return s;
   if ((int64_t)pb->r * o->restarts > 0x7fffffffLL) return ctx->fail(SYMTD_EINVAL, "r * restarts too large");
+  if (!(o->sigma >= 0.0) || !std::isfinite(o->sigma)) return ctx->fail(SYMTD_EINVAL, "sigma must be finite and >= 0");
+  if (o->sigma > 0.0 && ((pb->d != 3 && pb->d != 4) || pb->n > CORR_NMAX))
+    return ctx->fail(SYMTD_EINVAL, "the noise correction is derived for d = 3 and d = 4 (n <= %d)", CORR_NMAX);
   return SYMTD_OK;
 }
 
@@ -111,6 +122,9 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
   hipError_t e;
 
   SolveLayout<T> Lay;
+  Lay.corr = o.sigma > 0.0;
+  Lay.d4 = d == 4;
+  Lay.p = p;
   Lay.carve(nullptr, N, n, r, R, m, nb, trace_len);
   symtd_status s = ctx->reserve_solver(Lay.bytes);
   if (s != SYMTD_OK) return s;
@@ -131,6 +145,16 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
     if (!(alpha > 0.0 && std::isfinite(alpha))) return ctx->fail(SYMTD_ENONFINITE, "||X||^2 = %g is not positive", alpha);
   } else if (o.alpha_mode == SYMTD_ALPHA_GIVEN) {
     alpha = o.alpha;
+  }
+  // noise correction: the data's statistics, and alpha_c from alpha
+  const Correction corr{Lay.cm, Lay.cM2, o.sigma, d};
+  if (Lay.corr) {
+    launch_stats<T>(st, V, pb.ldv, pb.nu, n, p, Lay.cm, d == 4 ? Lay.cM2 : nullptr);
+    if (o.alpha_mode == SYMTD_ALPHA_COMPUTE) {
+      if ((s = corrected_alpha<T>(ctx, st, corr, V, pb.ldv, pb.nu, n, p, alpha, &alpha, Lay.cxd)) != SYMTD_OK) return s;
+      if (!(alpha > 0.0 && std::isfinite(alpha)))
+        return ctx->fail(SYMTD_ENONFINITE, "||X - Delta||^2 = %g is not positive", alpha);
+    }
   }
   const double scale = alpha > 0.0 ? alpha : 1.0;
 
@@ -187,6 +211,9 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
       if ((s = run_fg<T>(ctx, st, V, pb.ldv, pb.nu, n, p, Lay.A_t, n, Lay.lam_t, r, R, d, alpha, Lay.f_t, Lay.glam_t,
                          Lay.G_t, n)) != SYMTD_OK)
         return s;
+      if (Lay.corr)
+        launch_correction<T>(st, corr, Lay.A_t, n, (int)n, (int)r, R, Lay.lam_t, Lay.f_t, Lay.glam_t, Lay.G_t, n,
+                             Lay.clc);
       launch_lb_dots<T>(nb, R, st, Lay.lanes);
       launch_lb_step<T>(R, st, Lay.lanes, prm);
       launch_lb_apply<T>(nb, R, st, Lay.lanes);
@@ -226,7 +253,9 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
   // the reported f and relative error come from an fp64 evaluation at the
   // best restart's final point (the working precision may be fp32)
   double f64 = 0.0;
-  if ((s = final_fp64<T>(ctx, st, V, pb.ldv, pb.nu, n, p, B.A_t, n, B.lam_t, r, d, alpha, &f64)) != SYMTD_OK) return s;
+  if ((s = final_fp64<T>(ctx, st, V, pb.ldv, pb.nu, n, p, B.A_t, n, B.lam_t, r, d, alpha, &f64,
+                         Lay.corr ? &corr : nullptr)) != SYMTD_OK)
+    return s;
   out->f = f64;
   out->alpha = alpha;
   out->rel_err = alpha > 0.0 ? std::sqrt(std::max(out->f, 0.0) / alpha) : NAN;
@@ -258,6 +287,7 @@ symtd_status symtd_solve_opts_default(symtd_solve_opts* o) {
   o->alpha = 0.0;
   o->A0 = nullptr;
   o->check_every = 0;
+  o->sigma = 0.0;
   return SYMTD_OK;
 }
 

@@ -68,7 +68,7 @@ def test_struct_layouts_match_header(tmp_path):
     checks = {
         "symtd_problem": (S.Problem, ["dt", "V", "ldv", "nu", "n", "p", "d", "r"]),
         "symtd_solve_opts": (S.SolveOpts, ["prec", "m", "pgtol", "ftol", "max_iters", "max_evals", "restarts",
-                                           "seed", "init", "alpha_mode", "alpha", "A0", "check_every"]),
+                                           "seed", "init", "alpha_mode", "alpha", "A0", "check_every", "sigma"]),
         "symtd_fg_item": (S.FgItem, ["V", "ldv", "nu", "n", "p", "d", "A", "lda", "lambda", "r", "models",
                                      "alpha", "f", "g_lambda", "G_A", "ldg"]),
         "symtd_adam_opts": (S.AdamOpts, ["prec", "samples", "est_samples", "epoch_len", "max_epochs", "lr0",

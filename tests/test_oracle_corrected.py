@@ -94,3 +94,36 @@ def test_sigma_zero_is_the_plain_objective():
         b = fg_implicit(V, nu, A, lam, d, 1.5)
         assert a.f == b.f
         assert np.array_equal(a.g_lambda, b.g_lambda) and np.array_equal(a.G_A, b.G_A)
+
+
+def test_corrected_fit_recovers_the_clean_moment():
+    # Gaussian mixture n = 10, r = 3, p = 40000, sigma = 0.5, d = 3: the rank-r
+    # fit of X - Delta lies far closer to sum_j w_j mu_j^{(x)3} than the fit of X
+    from oracle import lbfgs as L
+    from oracle.normx import normx_implicit
+    from oracle.solve import INIT_RRF, pack, solve, start, unpack
+    import synth
+    n, r, p, sigma, d = 10, 3, 40000, 0.5, 3
+    V, nu, means = synth.gmm(n, r, p, sigma, 91, d)
+    w = np.bincount((np.arange(p) * r) // p, minlength=r) / p
+    C = T.kruskal(w, means, d)
+    alpha = normx_implicit(V, nu, d)
+    m, M2 = Cr.stats(V, nu)
+    ac = Cr.alpha_corrected(V, nu, d, sigma, alpha, m, M2)
+    plain = solve(V, nu, d, r, alpha=alpha, restarts=2, seed=3, pgtol=1e-8, max_iters=2000)
+    best = None
+    for k in range(2):
+        def fun(x):
+            lam, A = unpack(x, n, r)
+            o = Cr.fg_corrected(V, nu, A, lam, d, sigma, ac, m, M2)
+            return o.f / ac, np.concatenate([o.g_lambda, o.G_A.reshape(-1, order="F")]) / ac
+        run = L.lbfgs(fun, pack(*start(V, r, INIT_RRF, 3, k)), pgtol=1e-8, max_iters=2000)
+        best = run if best is None or run.f < best.f else best
+
+    def dist(lam, A):
+        M = T.kruskal(lam, A, d)
+        return np.sqrt(T.inner(M - C, M - C) / T.inner(C, C))
+
+    e_plain = dist(plain.lam, plain.A)
+    e_corr = dist(*unpack(best.x, n, r))
+    assert e_corr < 0.1 and e_plain > 0.5

@@ -22,9 +22,8 @@ struct symtd_data {
   int64_t ldv = 0;
   const double* nu = nullptr;
   int64_t n = 0, p = 0;
-  void* Vc = nullptr;            // 16-bit copies (see lp.hpp)
-  void* Vr = nullptr;
-  int64_t ldc = 0, ldr = 0, kc_len = 0, kr_len = 0, plane_c = 0, plane_r = 0;
+  void* Vc = nullptr;            // 16-bit copy (see lp.hpp)
+  int64_t ldc = 0, kc_len = 0, kr_len = 0, plane_c = 0;
   double wscale = 1.0;
 };
 
@@ -90,7 +89,7 @@ symtd_status run_fg_lp(symtd_ctx* ctx, hipStream_t st, const symtd_data* D, cons
   }
   for (int t0 = 0; t0 < nt_tot; t0 += LP_NT_MAX) {
     const int nt = std::min(LP_NT_MAX, nt_tot - t0);
-    LpG2Args a2{D->Vr, D->ldr, D->kr_len, D->plane_r, W, wplane, (int)n, 16 * t0, rp, nslab2, nsplit, cps, Ypart, npad};
+    LpG2Args a2{D->Vc, D->ldc, D->kr_len, D->plane_c, W, wplane, (int)n, 16 * t0, rp, nslab2, nsplit, cps, Ypart, npad};
     ctx->prof_begin(1, st);
     launch_lp_gemm2(kind, nt, dim3((unsigned)(nslab2 * 8 * ((nsplit + 7) / 8))), st, a2);
     ctx->prof_end(1, st);
@@ -138,18 +137,14 @@ symtd_status symtd_data_create(symtd_ctx* ctx, void* stream, symtd_dtype dt, con
     D->kc_len = LP_PAD * ((n + LP_PAD - 1) / LP_PAD);
     D->kr_len = LP_PAD * ((p + LP_PAD - 1) / LP_PAD);
     D->ldc = D->kc_len + LP_SKEW;
-    D->ldr = D->kr_len + LP_SKEW;
-    D->plane_c = D->ldc * p;
-    D->plane_r = n * D->ldr;
+    D->plane_c = D->ldc * D->kr_len;
     hipError_t e;
-    if ((e = hipMalloc(&D->Vc, sizeof(uint16_t) * PL * D->plane_c)) != hipSuccess ||
-        (e = hipMalloc(&D->Vr, sizeof(uint16_t) * PL * D->plane_r)) != hipSuccess) {
+    if ((e = hipMalloc(&D->Vc, sizeof(uint16_t) * PL * D->plane_c)) != hipSuccess) {
       (void)hipGetLastError();
       symtd_data_destroy(D);
-      return ctx->fail(SYMTD_ENOMEM, "device copies of V (%lld x %lld, 16-bit)", (long long)n, (long long)p);
+      return ctx->fail(SYMTD_ENOMEM, "device copy of V (%lld x %lld, 16-bit)", (long long)n, (long long)p);
     }
-    LpConvArgs ca{(const float*)V, ldv, (int)n, (int)p, D->Vc, D->ldc, D->kc_len, D->Vr, D->ldr, D->kr_len,
-                  D->plane_c, D->plane_r};
+    LpConvArgs ca{(const float*)V, ldv, (int)n, (int)p, D->Vc, D->ldc, D->kc_len, D->kr_len, D->plane_c};
     launch_lp_convert(D->kind, st, ca);
     // W is stored times 2^s with 2^s max(nu) in [1, 2) so that fp16 keeps it normal
     double* dmax = nullptr;
@@ -180,7 +175,6 @@ void symtd_data_destroy(symtd_data* D) {
   if (!D) return;
   (void)hipSetDevice(D->device);
   if (D->Vc) (void)hipFree(D->Vc);
-  if (D->Vr) (void)hipFree(D->Vr);
   delete D;
 }
 

@@ -9,12 +9,12 @@
 // 2^s in fp64.
 //
 // Layout (prepared once per data set, see symtd_data_create):
-//   Vc  column-major n x p: kc_len = n rounded up to LP_PAD covariates per
-//       column (rows past n zero), column stride ldc = kc_len + LP_SKEW: the
-//       first product's operand (covariates contiguous)
-//   Vr  row-major n x p: kr_len = p rounded up to LP_PAD observations per row
-//       (columns past p zero), row stride ldr = kr_len + LP_SKEW: the second
-//       product's operand (observations contiguous)
+//   Vc  column-major n x kr_len: kc_len = n rounded up to LP_PAD covariates
+//       per column (rows past n zero), kr_len = p rounded up to LP_PAD
+//       columns (columns past p zero), column stride ldc = kc_len + LP_SKEW.
+//       Both products read this one copy: the first with covariates as its
+//       k dimension, the second with observations as k, taking its operand
+//       fragments out of LDS with transposed reads.
 // per evaluation:
 //   Ac  A as kc_len rows x rp columns (zero padded), stride ldc, like Vc
 //   W   unit-major kr_len x rp: observation l of column j at
@@ -55,12 +55,12 @@ constexpr int LP_STAGES = SYMTD_LP_STAGES;
 // k values per chunk: a run of SYMTD_LP_RUN (fp16) or SYMTD_LP_RUN_BF (bf16x3,
 // per plane) bytes per column
 constexpr int lp_chunk(int kind) { return (kind == LP_F16 ? SYMTD_LP_RUN : SYMTD_LP_RUN_BF) / 2; }
-constexpr int LP_PAD = 256;              // ldr / ldc multiple (whole chunks, whole slabs)
+constexpr int LP_PAD = 256;              // kc_len / kr_len multiple (whole chunks, whole slabs)
 
-// ldc / ldr are column / row strides; kc_len / kr_len (multiples of LP_PAD)
-// are the extents the products run over (zero beyond the data).  The strides
-// exceed the extents by LP_SKEW elements so that a chunk's column reads do not
-// fall on a power-of-two stride.
+// ldc is the column stride; kc_len / kr_len (multiples of LP_PAD) are the
+// extents the products run over (zero beyond the data).  The stride exceeds
+// kc_len by LP_SKEW elements so that a chunk's column reads do not fall on a
+// power-of-two stride.
 constexpr int LP_SKEW = 64;
 
 struct LpG1Args {
@@ -75,7 +75,7 @@ struct LpG1Args {
 };
 
 struct LpG2Args {
-  const void* Vr; int64_t ldr; int64_t kr_len; int64_t vplane;
+  const void* Vc; int64_t ldc; int64_t kr_len; int64_t vplane;
   const void* W; int64_t wplane;
   int n; int col0; int rp;
   int nslab;                                     // ceil(n / LP_SLAB)
@@ -90,7 +90,7 @@ struct LpPackArgs {
 
 struct LpConvArgs {
   const float* V; int64_t ldv; int n; int p;
-  void* Vc; int64_t ldc; int64_t kc_len; void* Vr; int64_t ldr; int64_t kr_len; int64_t plane_c, plane_r;
+  void* Vc; int64_t ldc; int64_t kc_len; int64_t kr_len; int64_t plane_c;
 };
 
 void launch_lp_gemm1(int kind, int nt, dim3 grid, hipStream_t st, const LpG1Args& a);

@@ -1,15 +1,22 @@
 // fp16 / bf16x3 products of the evaluation (see lp.hpp).
 //
-// Both products are "k-contiguous" matrix-core products: every operand
-// column holds its k values contiguously, so a lane's MFMA operand (8
-// consecutive k values, 16 bytes) is one vector from LDS.  Chunks of each
-// column move from HBM to LDS as 16-byte pieces by direct global-to-LDS
-// loads (every thread moves the same number of pieces; the piece for LDS slot
-// s is chosen so that it lands on s), two LDS stages alternate, and LDS slots
-// are XOR-swizzled so that the 16 columns of a fragment read hit distinct
-// banks.  The MFMA is v_mfma_f32_16x16x32_{f16,bf16}: lane 16 g + c supplies
-// row c and k values 8 g .. 8 g + 7 of a 32-deep step, and holds output rows
-// 4 g .. 4 g + 3 of column c.
+// The MFMA is v_mfma_f32_16x16x32_{f16,bf16}: lane 16 g + c supplies row c
+// and k values 8 g .. 8 g + 7 of a 32-deep step, and holds output rows
+// 4 g .. 4 g + 3 of column c.  Chunks of the operands move from HBM to LDS as
+// 16-byte pieces by direct global-to-LDS loads (every thread moves the same
+// number of pieces; the piece for LDS slot s is chosen so that it lands on
+// s), and two LDS stages alternate.
+//
+// The first product is "k-contiguous": every operand column of Vc (an
+// observation) and of Ac holds its k values (covariates) contiguously, so a
+// lane's operand is one 16-byte LDS vector; slots are XOR-swizzled so that
+// the 16 columns of a fragment read hit distinct banks.  The second product
+// reads the same Vc with observations as k: a chunk holds, for each of its
+// observations, the 8-covariate units of the block's row slab, and a lane's
+// operand (8 observations of one covariate) comes from two transposed
+// 8-byte LDS reads (ds_read_b64_tr_b16: in each group of 16 lanes, lane c
+// receives element c mod 4 of the words of lanes c / 4, 4 + c / 4, 8 + c / 4
+// and 12 + c / 4, checked on the hardware), so V is stored once.
 #include <type_traits>
 
 #include "kcommon.hpp"
@@ -24,6 +31,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 template <int KIND> struct LpT;
 template <> struct LpT<LP_F16> {
@@ -87,19 +95,42 @@ struct LpStage {
   }
 };
 
-// DMA of chunk kc: slab operand rows xcol(col) (plane stride xplane) and
-// column operand columns ycol(col); k offset k0 (elements)
-template <int KIND, int NT, typename XF, typename YF>
+// The second product's slab operand in LDS: for each observation k of the
+// chunk (row k), the LP_SLAB / 8 = 16 units of 8 covariates of the block's
+// slab; unit qc of row k is stored at unit qc ^ 2 sigma(k) of the row, with
+// sigma(k) = (k mod 4) + 4 ((k / 4 + k / 8) mod 2).  A transposed read of
+// one fragment touches rows k0 + j (j < 4) in each 16-lane group g (k0 = 8 g
+// or 8 g + 4), two units per row: the four rows of a group land on four
+// distinct unit pairs, and groups g and g + 1 on the two halves of the row,
+// so a 16-lane group covers every bank of a 128-byte row once and a
+// 32-lane half-wave every bank of a 256-byte row once.
+struct TrSwz {
+  static constexpr int UPR = LP_SLAB / 8;
+  static_assert(UPR == 16, "the transposed-read swizzle is written for 16 units per row");
+  static __device__ __forceinline__ int sig2(int k) { return 2 * ((k & 3) | ((((k >> 2) ^ (k >> 3)) & 1) << 2)); }
+  static __device__ __forceinline__ int slot(int k, int qc) { return k * UPR + (qc ^ sig2(k)); }
+  static __device__ __forceinline__ void unslot(int s, int& k, int& qc) {
+    k = s / UPR;
+    qc = (s % UPR) ^ sig2(k);
+  }
+};
+
+// DMA of one chunk: the slab operand's pieces xsrc(plane, col, unit) (for
+// TR, col is the chunk's observation and unit its 8-covariate unit) and the
+// column operand's pieces ysrc(plane, col, unit)
+template <int KIND, int NT, bool TR, typename XF, typename YF>
 __device__ __forceinline__ void lp_dma(u4* lx, u4* ly, int tid, int wave, XF xsrc, YF ysrc) {
   using S = LpStage<KIND, NT>;
+  constexpr int PU = S::XU / S::PL;                              // units per plane
 #pragma unroll
   for (int i = 0; i < S::XP; ++i) {
     const int P = tid + 256 * i;
     const void* src = xsrc(0, 0, 0);                             // padding pieces: any valid address
     if (P < S::XU) {
-      const int pl = P / (LP_SLAB * S::U);
+      const int pl = P / PU;
       int col, q;
-      S::unswz(P % (LP_SLAB * S::U), col, q);
+      if constexpr (TR) TrSwz::unslot(P % PU, col, q);
+      else S::unswz(P % PU, col, q);
       src = xsrc(pl, col, q);
     }
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)((char*)lx + 16 * (256 * i + 64 * wave)),
@@ -133,6 +164,55 @@ __device__ __forceinline__ void lp_compute(const u4* lx, const u4* ly, int wave,
     for (int m = 0; m < LP_MT; ++m)
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl) fv[b][m][pl] = lx[pl * LP_SLAB * S::U + S::swz(16 * (LP_MT * wave + m) + c, q)];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) fa[b][t][pl] = ly[pl * 16 * NT * S::U + S::swz(16 * t + c, q)];
+  };
+  frag(0, 0);
+#pragma unroll
+  for (int jg = 0; jg < J; ++jg) {
+    if (jg + 1 < J) frag((jg + 1) & 1, jg + 1);
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = LpT<KIND>::mac(fv[jg & 1][m], fa[jg & 1][t], acc[m][t]);
+  }
+}
+
+// multiply one chunk of the second product held in LDS into acc: the slab
+// operand by transposed reads, the column operand (W) as in lp_compute
+template <int KIND, int NT>
+__device__ __forceinline__ void lp_compute_tr(const u4* lx, const u4* ly, int wave, int g, int c,
+                                              f4 (&acc)[LP_MT][NT]) {
+  using S = LpStage<KIND, NT>;
+  constexpr int PL = S::PL;
+  constexpr int J = S::U / 4;
+  constexpr int PU = S::XU / PL;
+  typedef short s4 __attribute__((ext_vector_type(4)));
+  u4 fv[2][LP_MT][PL], fa[2][NT][PL];
+  // lane c of group g points at observation k0 + c / 4, covariates
+  // 4 (c mod 4) .. + 3 of the subtile, i.e. unit c mod 4 / 2, half c mod 2
+  const int krow = 8 * g + (c >> 2);
+  const int qoff = (c & 3) >> 1;
+  const int boff = 8 * (c & 1);
+  auto frag = [&](int b, int jg) {
+    const int q = 4 * jg + g;
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) {
+        s4 h[2];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int k = 32 * jg + krow + 4 * hh;
+          const int qc = 2 * (LP_MT * wave + m) + qoff;
+          const char* addr = (const char*)(lx + pl * PU + TrSwz::slot(k, qc)) + boff;
+          h[hh] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s4*)addr);
+        }
+        const u2 lo = __builtin_bit_cast(u2, h[0]), hi = __builtin_bit_cast(u2, h[1]);
+        fv[b][m][pl] = u4{lo[0], lo[1], hi[0], hi[1]};
+      }
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -242,7 +322,7 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
     auto ys = [&](int pl, int col, int q) -> const void* {
       return Ac + pl * a.aplane + (int64_t)(a.col0 + col) * a.ldc + k0 + 8 * q;
     };
-    lp_dma<KIND, NT>(lx, ly, tid, wave, xs, ys);
+    lp_dma<KIND, NT, false>(lx, ly, tid, wave, xs, ys);
   };
 
   // weights of the slab being multiplied, for its owner's epilogue: loaded
@@ -375,8 +455,8 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// gemm2: partial Y = Vr W over one split of the observations, one block per
-// (row slab, split); rows past n are computed from a clamped row and not read
+// gemm2: partial Y = V W over one split of the observations, one block per
+// (row slab, split), reading Vc; rows past n are zero in Vc and not read
 // ---------------------------------------------------------------------------
 template <int KIND, int NT>
 __global__ __launch_bounds__(256) void k_lp_gemm2(LpG2Args a) {
@@ -398,7 +478,7 @@ __global__ __launch_bounds__(256) void k_lp_gemm2(LpG2Args a) {
   const int64_t KC = a.kr_len / KCH;
   const int64_t kb = (int64_t)split * a.chunks_per_split;
   const int64_t ke = min(KC, kb + a.chunks_per_split);
-  const E* Vr = (const E*)a.Vr;
+  const E* Vc = (const E*)a.Vc;
   const E* W = (const E*)a.W;
   f4 acc[LP_MT][NT];
 #pragma unroll
@@ -407,19 +487,18 @@ __global__ __launch_bounds__(256) void k_lp_gemm2(LpG2Args a) {
     for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
   auto dma = [&](u4* lx, u4* ly, int64_t kc) {
     const int64_t k0 = kc * KCH;
-    auto xs = [&](int pl, int col, int q) -> const void* {
-      int64_t i = (int64_t)LP_SLAB * slab + col;
-      i = i < a.n ? i : (int64_t)a.n - 1;
-      return Vr + pl * a.vplane + i * a.ldr + k0 + 8 * q;
+    // piece (observation k0 + k, covariate unit q of the slab)
+    auto xs = [&](int pl, int k, int q) -> const void* {
+      return Vc + pl * a.vplane + (k0 + k) * a.ldc + (int64_t)LP_SLAB * slab + 8 * q;
     };
     auto ys = [&](int pl, int col, int q) -> const void* {
       return W + pl * a.wplane + ((k0 >> 3) + q) * (int64_t)a.rp * 8 + (int64_t)(a.col0 + col) * 8;
     };
-    lp_dma<KIND, NT>(lx, ly, tid, wave, xs, ys);
+    lp_dma<KIND, NT, true>(lx, ly, tid, wave, xs, ys);
   };
   const int64_t nk = ke - kb;
   chunk_loop(nk, [&](u4* lx, u4* ly, int64_t q) { dma(lx, ly, kb + q); },
-             [&](const u4* lx, const u4* ly) { lp_compute<KIND, NT>(lx, ly, wave, g, c, acc); });
+             [&](const u4* lx, const u4* ly) { lp_compute_tr<KIND, NT>(lx, ly, wave, g, c, acc); });
   // acc[m][t][v] = Y[slab rows + 16 (MT wave + m) + 4 g + v][col0 + 16 t + c]
 #pragma unroll
   for (int m = 0; m < LP_MT; ++m) {
@@ -464,43 +543,19 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_lp_prep(LpPackArgs pk, int64_t
   gram_tile(gram, b - npack, lds);
 }
 
-// Vc (column-major, ld ldc) elementwise; Vr (row-major, ld ldr) through
-// 32 x 32 LDS tiles so that both sides are read and written in rows
+// Vc (column-major, ld ldc, kr_len columns) elementwise, zero past n and p
 template <int KIND>
 __global__ __launch_bounds__(256) void k_lp_conv_c(LpConvArgs a) {
   using E = typename LpT<KIND>::E;
   constexpr int PL = LpT<KIND>::PLANES;
-  const int64_t total = (int64_t)a.p * a.kc_len;
+  const int64_t total = a.kr_len * a.kc_len;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t l = e / a.kc_len, k = e - l * a.kc_len;
-    const double x = k < a.n ? (double)a.V[l * a.ldv + k] : 0.0;
+    const double x = (k < a.n && l < a.p) ? (double)a.V[l * a.ldv + k] : 0.0;
     E parts[PL];
     LpT<KIND>::split(x, parts);
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) ((E*)a.Vc)[pl * a.plane_c + l * a.ldc + k] = parts[pl];
-  }
-}
-
-template <int KIND>
-__global__ __launch_bounds__(256) void k_lp_conv_r(LpConvArgs a) {
-  using E = typename LpT<KIND>::E;
-  constexpr int PL = LpT<KIND>::PLANES;
-  __shared__ float tile[32][33];
-  const int64_t l0 = (int64_t)blockIdx.x * 32, i0 = (int64_t)blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 32 x 8
-  for (int yy = ty; yy < 32; yy += 8) {
-    const int64_t l = l0 + yy, i = i0 + tx;
-    tile[yy][tx] = (l < a.p && i < a.n) ? a.V[l * a.ldv + i] : 0.0f;
-  }
-  __syncthreads();
-  for (int yy = ty; yy < 32; yy += 8) {
-    const int64_t i = i0 + yy, l = l0 + tx;
-    if (i < a.n && l < a.kr_len) {
-      E parts[PL];
-      LpT<KIND>::split((double)tile[tx][yy], parts);
-#pragma unroll
-      for (int pl = 0; pl < PL; ++pl) ((E*)a.Vr)[pl * a.plane_r + i * a.ldr + l] = parts[pl];
-    }
   }
 }
 
@@ -565,16 +620,10 @@ void launch_lp_prep(int kind, int64_t gram_blocks, hipStream_t st, const LpPackA
   else hipLaunchKernelGGL(k_lp_prep<LP_BF16X3>, grid, dim3(GRAM_THREADS), 0, st, a, npack, g);
 }
 void launch_lp_convert(int kind, hipStream_t st, const LpConvArgs& a) {
-  const int64_t total = (int64_t)a.p * a.kc_len;
+  const int64_t total = a.kr_len * a.kc_len;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-  const dim3 tgrid((unsigned)((a.kr_len + 31) / 32), (unsigned)((a.n + 31) / 32));
-  if (kind == LP_F16) {
-    hipLaunchKernelGGL(k_lp_conv_c<LP_F16>, dim3(blocks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_lp_conv_r<LP_F16>, tgrid, dim3(256), 0, st, a);
-  } else {
-    hipLaunchKernelGGL(k_lp_conv_c<LP_BF16X3>, dim3(blocks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_lp_conv_r<LP_BF16X3>, tgrid, dim3(256), 0, st, a);
-  }
+  if (kind == LP_F16) hipLaunchKernelGGL(k_lp_conv_c<LP_F16>, dim3(blocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_lp_conv_c<LP_BF16X3>, dim3(blocks), dim3(256), 0, st, a);
 }
 void launch_max_abs(hipStream_t st, const double* x, int64_t count, double* out) {
   hipLaunchKernelGGL(k_max_abs, dim3(1), dim3(256), 0, st, x, count, out);

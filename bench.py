@@ -564,7 +564,11 @@ def batched_leg(S, ctx, count, pgtol):
             "rel_err": rel_err_summary(rb, sigma), "rel_err_loop": rel_err_summary(rl, sigma),
             "rel_err_abs_diff_vs_loop": delta_summary(rb, rl),
             "exit": exit_histogram(S, res), "exit_loop": exit_histogram(S, lo),
-            "evals_median": float(np.median([r["evals"] for r in res]))}
+            "evals_median": float(np.median([r["evals"] for r in res])),
+            # a problem leaves the batch at the step its last restart stops:
+            # every live restart takes one evaluation per step
+            "finish_step_q50_q90_q99_max": [float(x) for x in np.quantile(
+                [max(r["evals_restarts"]) for r in res], [0.5, 0.9, 0.99, 1.0])]}
 
 
 def served_leg(S, ctx, count, rate, pgtol):

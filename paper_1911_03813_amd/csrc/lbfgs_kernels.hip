@@ -299,18 +299,29 @@ __device__ void accept(LbState& s, const LbLane<T>& ln, const LbParams& prm, con
 
 }  // namespace
 
+// the line search and the new direction of one lane on its state s (staged in
+// LDS by k_lb_step) and the inner products D of this evaluation
+template <typename T>
+__device__ void lb_decide(LbState& s, const LbLane<T>& ln, const LbParams& prm, const double* D);
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbParams prm) {
   const int L = blockIdx.x;
   const LbLane<T> ln = lanes[L];
-  LbState& s = *ln.state;
-  if (s.phase == LB_DONE) {
+  if (ln.state->phase == LB_DONE) {
     if (threadIdx.x == 0) {
-      s.action = LB_NONE;
+      ln.state->action = LB_NONE;
       if (ln.done_flag) *ln.done_flag = 1;   // kept raised (tables may have been rebuilt)
     }
     return;
   }
+  // the state moves to LDS with one load per word across the block, so that
+  // the serial logic below waits on LDS rather than on a chain of global loads
+  static_assert(sizeof(LbState) % 8 == 0, "LbState is copied in 8-byte words");
+  constexpr int NW = (int)(sizeof(LbState) / 8);
+  __shared__ LbState sh;
+  for (int i = threadIdx.x; i < NW; i += 64)
+    reinterpret_cast<uint64_t*>(&sh)[i] = gload(reinterpret_cast<const uint64_t*>(ln.state) + i);
   __shared__ double D[LB_ND];
   if (threadIdx.x < LB_ND) {
     const int i = threadIdx.x;
@@ -328,8 +339,14 @@ __global__ __launch_bounds__(64) void k_lb_step(const LbLane<T>* lanes, LbParams
     D[i] = v;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x == 0) lb_decide<T>(sh, ln, prm, D);
+  __syncthreads();
+  for (int i = threadIdx.x; i < NW; i += 64)
+    gstore(reinterpret_cast<uint64_t*>(ln.state) + i, reinterpret_cast<const uint64_t*>(&sh)[i]);
+}
 
+template <typename T>
+__device__ void lb_decide(LbState& s, const LbLane<T>& ln, const LbParams& prm, const double* D) {
   const double phi = ln.f_t[0] / ln.scale;
   const double gtd = D[LB_GTD];
   s.evals += 1;

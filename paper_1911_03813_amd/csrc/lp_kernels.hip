@@ -418,9 +418,9 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
 
   if (u0 < u1) {
     // the block's (slab, chunk) units in order through one continuous
-    // two-stage pipeline: a slab's epilogue runs while the next chunk (the
-    // next slab's first) is already in flight
-    static_assert(LP_STAGES == 2, "the first product's unit loop is written for two stages");
+    // two-stage pipeline (whatever LP_STAGES says for the second product): a
+    // slab's epilogue runs while the next chunk (the next slab's first) is
+    // already in flight
     // (slab, chunk) of the unit being multiplied and of the next one issued
     int64_t sl = u0 / KC, kc = u0 - sl * KC;
     int64_t isl = sl, ikc = kc;

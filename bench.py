@@ -25,6 +25,9 @@ implicit (Algorithm 2) evaluation at Table 1's scenarios, fp64.
 "stochastic": Section 5's comparison at d=3, n=500, r=10, p=500,000,
 sigma=0.1: L-BFGS on the full data against Adam on s in {10, 100, 1000}
 sampled columns per step, from the same ten starts.
+"corrected": moments corrected for spherical Gaussian noise (n=50, r=5,
+p=100,000, sigma=0.3, d in {3, 4}, fp64): plain against corrected solves,
+with the similarity score and the distance from the noiseless moment.
 "batched": 512 problems, n ~ U{16..256}, r ~ U{2..32}, p = 250 r, d in
 {3, 4}, sigma in {1e-3, 1e-2}, 4 randomized-range-finder restarts each, fp32,
 solved together by symtd_solve_batched, against the plain loop of
@@ -35,7 +38,8 @@ the plain first-in-first-out loop of symtd_solve calls replaying the same
 arrival trace.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|fp16|bf16x3]
-                    [--no-cpu-baseline] [--only-fg] [--batched N] [--served N]
+                    [--no-cpu-baseline] [--only-fg] [--legs a,b,...] [--batched N]
+                    [--batched-max-evals K] [--no-batched-loop] [--served N] [--study]
 """
 
 from __future__ import annotations
@@ -67,11 +71,11 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
                    "paper_1911_03813_amd/csrc/kcommon.hpp", "paper_1911_03813_amd/csrc/lp_kernels.hip",
                    "paper_1911_03813_amd/csrc/lp.hpp")
-TRAFFIC_SHA = "24cc126df2bade14"
-TRAFFIC_BYTES = {("fp32", "gemm1"): 506.4e6, ("fp32", "gemm2"): 475.4e6,
-                 ("fp64", "gemm1"): 1089.4e6, ("fp64", "gemm2"): 948.5e6,
-                 ("fp16", "gemm1"): 269.6e6, ("fp16", "gemm2"): 237.6e6,
-                 ("bf16x3", "gemm1"): 501.8e6, ("bf16x3", "gemm2"): 460.1e6}
+TRAFFIC_SHA = "1e080b401d76ef55"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 506.4e6, ("fp32", "gemm2"): 475.2e6,
+                 ("fp64", "gemm1"): 1089.8e6, ("fp64", "gemm2"): 948.5e6,
+                 ("fp16", "gemm1"): 269.6e6, ("fp16", "gemm2"): 242.3e6,
+                 ("bf16x3", "gemm1"): 501.7e6, ("bf16x3", "gemm2"): 469.7e6}
 
 
 def traffic_for(prec, kernel):
@@ -107,6 +111,13 @@ def parse():
     ap.add_argument("--g2-splits", type=int, default=0)
     ap.add_argument("--only-fg", action="store_true", help="headline only (no batched/served legs)")
     ap.add_argument("--batched", type=int, default=512, help="problems of the batched leg")
+    ap.add_argument("--batched-max-evals", type=int, default=0,
+                    help="cap every batched problem's evaluations (0 = the solver's default); with a small cap "
+                         "every problem stays in the batch, so a profile sees full steps only")
+    ap.add_argument("--no-batched-loop", action="store_true", help="skip the plain loop beside the batched leg")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs after the headline (precisions, normx, small, mid, table1, "
+                         "stochastic, corrected, batched, served) or all")
     ap.add_argument("--served", type=int, default=600, help="requests of the served leg")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the served leg (requests/s)")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_1911_03813_amd", "tuning", "mi355x.json"),
@@ -171,8 +182,9 @@ def cpu_baseline(V64, nu, A64, lam, d, seconds):
     return out
 
 
-def grouped_problems(count, key, pgtol, restarts=4):
-    """Problems of the grouped workload (device tensors) and their sigmas."""
+def grouped_problems(count, key, pgtol, restarts=4, max_evals=0):
+    """Problems of the grouped workload (device tensors) and their sigmas
+    (max_evals > 0 caps every problem's evaluations)."""
     import torch
 
     import paper_1911_03813_amd as S
@@ -182,6 +194,8 @@ def grouped_problems(count, key, pgtol, restarts=4):
         V, nu, _ = synth.gmm(s["n"], s["r"], s["p"], s["sigma"], key, i)
         probs.append(dict(V=S.colmajor(torch.from_numpy(V).float()).cuda(), nu=torch.from_numpy(nu).cuda(),
                           d=s["d"], r=s["r"], restarts=restarts, seed=1000 + i, pgtol=pgtol))
+        if max_evals > 0:
+            probs[-1]["max_evals"] = max_evals
     return probs, np.array([s["sigma"] for s in shapes])
 
 
@@ -237,9 +251,18 @@ def normx_leg(S, ctx, Vs, nu, d, reps=3):
     t = (time.perf_counter() - t0) / reps
     flop = float(n) * p * (p + 1)
     peak = PEAK_TFLOPS["fp64"]
-    return {"workload": f"d={d} n={n} p={p}, fp32 storage, fp64 matrix products", "calls": reps,
-            "ms_per_call": t * 1e3, "tflops": flop / t / 1e12, "peak_tflops": peak,
-            "frac": flop / t / 1e12 / peak}
+    out = {"workload": f"d={d} n={n} p={p}, fp32 storage, fp64 matrix products", "calls": reps,
+           "ms_per_call": t * 1e3, "tflops": flop / t / 1e12, "peak_tflops": peak,
+           "frac": flop / t / 1e12 / peak, "value": float(a.cpu()[0])}
+    # the oracle's value of the same data set, stored by tests/golden/make_normx_full.py
+    gold = os.path.join(ROOT, "tests", "golden", "normx_gmm_n1000_p1e5_d3.json")
+    if os.path.exists(gold):
+        with open(gold) as fh:
+            g = json.load(fh)
+        if (g["workload"]["n"], g["workload"]["p"], g["workload"]["d"]) == (n, p, d):
+            out["oracle_value"] = g["value"]
+            out["error_vs_oracle_rel_scale"] = abs(out["value"] - g["value"]) / g["scale_abs"]
+    return out
 
 
 def precision_leg(S, ctx, Vs, nu, As, lam, d, steps, warmup):
@@ -424,6 +447,45 @@ def stoch_leg(S, ctx, pgtol):
     return out
 
 
+def corrected_leg(S, ctx, pgtol):
+    """Moments corrected for spherical Gaussian noise of known level: a
+    Gaussian mixture (n=50, r=5, p=100,000, sigma=0.3, congruent means) at
+    d = 3 and 4, solved with 5 RRF restarts in fp64 on the plain objective
+    and on the corrected one.  For each: wall time, the similarity score
+    against the true means, and the relative distance of the model from the
+    noiseless moment C = sum_j w_j mu_j^{(x)d}, from the Kruskal identity
+    <sum_j l_j a_j^d, sum_k w_k u_k^d> = l' [A'U]^d w (no tensor formed)."""
+    import torch
+    n, r, p, sigma = 50, 5, 100_000, 0.3
+    out = {"workload": f"Gaussian mixture n={n} r={r} p={p} sigma={sigma}, congruent means, fp64, 5 RRF restarts",
+           "rows": []}
+    for d in (3, 4):
+        V, nu, means = synth.gmm(n, r, p, sigma, 18, d, congruent=True)
+        w = np.bincount((np.arange(p) * r) // p, minlength=r) / p
+        Vd = S.colmajor(torch.from_numpy(V)).cuda()
+        nud = torch.from_numpy(nu).cuda()
+
+        def dist(lam, A):
+            kr = lambda l1, A1, l2, A2: float(l1 @ (A1.T @ A2) ** d @ l2)
+            mm, mc, cc = kr(lam, A, lam, A), kr(lam, A, w, means), kr(w, means, w, means)
+            return float(np.sqrt(max(mm - 2 * mc + cc, 0.0) / cc))
+
+        row = {"d": d}
+        for name, sg in (("plain", 0.0), ("corrected", sigma)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = S.symtd_solve(ctx, Vd, nud, d, r, restarts=5, seed=51, pgtol=pgtol, sigma=sg)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            A = res["A"].cpu().numpy()
+            lam = res["lam"].cpu().numpy()
+            row[name] = {"seconds": sec, "evals": int(res["evals"]), "exit": S.EXIT_NAMES[int(res["exit_reason"])],
+                         "score": S.metrics.similarity_score(means, A), "dist_to_clean_moment": dist(lam, A)}
+        out["rows"].append(row)
+        del Vd
+    return out
+
+
 # Table 1's scenarios (d, n, p, r) and the paper's seconds per iteration
 # (explicit, implicit), MATLAB on the CPU it names: context only
 TABLE1 = [(3, 75, 750, 5, 5.30e-04, 4.36e-04), (3, 75, 750, 25, 1.91e-03, 5.91e-04),
@@ -539,36 +601,37 @@ def init_study(S, ctx, runs=100):
             "seconds": times, "rows": rows}
 
 
-def batched_leg(S, ctx, count, pgtol):
+def batched_leg(S, ctx, count, pgtol, max_evals=0, loop=True):
     import torch
-    probs, sigma = grouped_problems(count, 4, pgtol)
+    probs, sigma = grouped_problems(count, 4, pgtol, max_evals=max_evals)
     S.symtd_solve_batched(ctx, probs[:4])              # warm the path
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = S.symtd_solve_batched(ctx, probs)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    # the plain loop of symtd_solve calls on every problem of the batch
-    t0 = time.perf_counter()
-    lo = [loop_solve(S, ctx, pr) for pr in probs]
-    torch.cuda.synchronize()
-    tl = time.perf_counter() - t0
     rb = np.array([r["rel_err"] for r in res])
-    rl = np.array([r["rel_err"] for r in lo])
-    return {"workload": f"{count} problems n~U{{16..256}} r~U{{2..32}} p=250r d in {{3,4}} sigma in {{1e-3,1e-2}}, "
-                        f"4 restarts, fp32, pgtol {pgtol:g}",
-            "solves_per_s": count / tb, "restart_solves_per_s": 4 * count / tb,
-            "seconds": tb, "steps": int(res[0]["steps"]),
-            "loop": {"problems": count, "solves_per_s": count / tl, "seconds": tl},
-            "speedup_vs_loop": tl / tb,
-            "rel_err": rel_err_summary(rb, sigma), "rel_err_loop": rel_err_summary(rl, sigma),
-            "rel_err_abs_diff_vs_loop": delta_summary(rb, rl),
-            "exit": exit_histogram(S, res), "exit_loop": exit_histogram(S, lo),
-            "evals_median": float(np.median([r["evals"] for r in res])),
-            # a problem leaves the batch at the step its last restart stops:
-            # every live restart takes one evaluation per step
-            "finish_step_q50_q90_q99_max": [float(x) for x in np.quantile(
-                [max(r["evals_restarts"]) for r in res], [0.5, 0.9, 0.99, 1.0])]}
+    out = {"workload": f"{count} problems n~U{{16..256}} r~U{{2..32}} p=250r d in {{3,4}} sigma in {{1e-3,1e-2}}, "
+                       f"4 restarts, fp32, pgtol {pgtol:g}" + (f", at most {max_evals} evaluations" if max_evals else ""),
+           "solves_per_s": count / tb, "restart_solves_per_s": 4 * count / tb,
+           "seconds": tb, "steps": int(res[0]["steps"]),
+           "rel_err": rel_err_summary(rb, sigma), "exit": exit_histogram(S, res),
+           "evals_median": float(np.median([r["evals"] for r in res])),
+           # a problem leaves the batch at the step its last restart stops:
+           # every live restart takes one evaluation per step
+           "finish_step_q50_q90_q99_max": [float(x) for x in np.quantile(
+               [max(r["evals_restarts"]) for r in res], [0.5, 0.9, 0.99, 1.0])]}
+    if loop:
+        # the plain loop of symtd_solve calls on every problem of the batch
+        t0 = time.perf_counter()
+        lo = [loop_solve(S, ctx, pr) for pr in probs]
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        rl = np.array([r["rel_err"] for r in lo])
+        out.update({"loop": {"problems": count, "solves_per_s": count / tl, "seconds": tl},
+                    "speedup_vs_loop": tl / tb, "rel_err_loop": rel_err_summary(rl, sigma),
+                    "rel_err_abs_diff_vs_loop": delta_summary(rb, rl), "exit_loop": exit_histogram(S, lo)})
+    return out
 
 
 def served_leg(S, ctx, count, rate, pgtol):
@@ -838,18 +901,28 @@ def main():
         data.close()
     del Vd, Ad, out
     if not args.only_fg:
+        legs = set(args.legs.split(",")) if args.legs != "all" else None
+        want = lambda name: legs is None or name in legs
         V32 = V.astype(np.float32).astype(np.float64)
         A32 = A.astype(np.float32).astype(np.float64)
-        res["precisions"] = precision_leg(S, ctx, V32, nu, A32, lam, d, args.steps, args.warmup)
-        res["normx"] = normx_leg(S, ctx, V32, nu, d)
-        res["small"] = small_leg(S, ctx)
-        res["mid"] = mid_leg(S, ctx, args.pgtol)
-        res["table1"] = table1_leg(S, ctx)
-        if not args.no_stoch:
+        if want("precisions"):
+            res["precisions"] = precision_leg(S, ctx, V32, nu, A32, lam, d, args.steps, args.warmup)
+        if want("normx"):
+            res["normx"] = normx_leg(S, ctx, V32, nu, d)
+        if want("small"):
+            res["small"] = small_leg(S, ctx)
+        if want("mid"):
+            res["mid"] = mid_leg(S, ctx, args.pgtol)
+        if want("table1"):
+            res["table1"] = table1_leg(S, ctx)
+        if want("stochastic") and not args.no_stoch:
             res["stochastic"] = stoch_leg(S, ctx, args.pgtol)
-        if args.batched > 0:
-            res["batched"] = batched_leg(S, ctx, args.batched, args.pgtol)
-        if args.served > 0:
+        if want("corrected"):
+            res["corrected"] = corrected_leg(S, ctx, args.pgtol)
+        if want("batched") and args.batched > 0:
+            res["batched"] = batched_leg(S, ctx, args.batched, args.pgtol, args.batched_max_evals,
+                                         not args.no_batched_loop)
+        if want("served") and args.served > 0:
             res["served"] = served_leg(S, ctx, args.served, args.rate, args.pgtol)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(Vs, nu, As, lam, d, args.cpu_seconds)

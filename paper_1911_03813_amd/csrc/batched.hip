@@ -118,10 +118,10 @@ symtd_status run_solve_batched(symtd_ctx* ctx, hipStream_t st, int64_t count, co
   while (eng.live() > 0) {
     if ((s = eng.run(K)) != SYMTD_OK) return s;
     if ((s = eng.poll(done)) != SYMTD_OK) return s;
-    for (auto* I : done) {
-      if ((s = eng.collect(I, &outs[I->id], false)) != SYMTD_OK) return s;
-      eng.remove(I);
-    }
+    std::vector<symtd_solve_result*> res;
+    for (auto* I : done) res.push_back(&outs[I->id]);
+    if ((s = eng.collect_many(done, res, false)) != SYMTD_OK) return s;
+    for (auto* I : done) eng.remove(I);
     if (eng.steps() > max_evals + 2 * K)
       return ctx->fail(SYMTD_EDEVICE, "batched solve did not stop within %lld steps", (long long)eng.steps());
   }

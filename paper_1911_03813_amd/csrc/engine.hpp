@@ -353,47 +353,94 @@ class GroupEngine {
     return SYMTD_OK;
   }
 
-  // Results of a finished instance (host figures; A and lambda to device or host buffers)
-  symtd_status collect(EngineInst<T>* I, symtd_solve_result* out, bool host_outputs) {
+  // Results of finished instances (host figures; A and lambda to device or
+  // host buffers).  The lane states of all of them come back in one round of
+  // copies with one wait; then every instance's result copies and its fp64
+  // evaluation at the best restart's point are enqueued, and one more wait
+  // brings all the f values back.
+  symtd_status collect_many(const std::vector<EngineInst<T>*>& set, const std::vector<symtd_solve_result*>& outs,
+                            bool host_outputs) {
+    if (set.empty()) return SYMTD_OK;
     hipError_t e;
-    std::vector<LbState> hs(I->R);
-    if ((e = hipMemcpyAsync(hs.data(), I->states, sizeof(LbState) * I->R, hipMemcpyDeviceToHost, st_)) != hipSuccess ||
-        (e = hipStreamSynchronize(st_)) != hipSuccess)
-      return ctx_->hip_fail(e, "engine collect");
-    int best = 0;
-    for (int k = 1; k < I->R; ++k)
-      if (hs[k].f < hs[best].f || (std::isnan(hs[best].f) && !std::isnan(hs[k].f))) best = k;
-    const LbLane<T>& B = I->lanes[best];
-    const hipMemcpyKind kind = host_outputs ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-    if ((e = hipMemcpy2DAsync(out->A, (size_t)out->lda * sizeof(T), B.A_t, (size_t)I->ld * sizeof(T),
-                              (size_t)I->n * sizeof(T), (size_t)I->r, kind, st_)) != hipSuccess ||
-        (e = hipMemcpyAsync(out->lambda, B.lam_t, sizeof(double) * I->r, kind, st_)) != hipSuccess)
-      return ctx_->hip_fail(e, "engine result copy");
-    if (out->f_trace && I->trace_len > 0 &&
-        (e = hipMemcpyAsync(out->f_trace, I->trace, sizeof(double) * I->R * I->trace_len, hipMemcpyDeviceToHost, st_)) !=
-            hipSuccess)
-      return ctx_->hip_fail(e, "engine trace copy");
-    if ((e = hipStreamSynchronize(st_)) != hipSuccess) return ctx_->hip_fail(e, "engine collect sync");
-    for (int k = 0; k < I->R; ++k) {
-      if (out->f_restarts) out->f_restarts[k] = hs[k].f * I->scale;
-      if (out->iters_restarts) out->iters_restarts[k] = hs[k].iters;
-      if (out->evals_restarts) out->evals_restarts[k] = hs[k].evals;
-      if (out->exit_restarts) out->exit_restarts[k] = hs[k].reason;
+    size_t nst = 0;
+    for (auto* I : set) nst += (size_t)I->R;
+    const size_t need = nst * sizeof(LbState) + set.size() * sizeof(double);
+    if (need > pin_bytes_) {
+      if (pin_) (void)hipHostFree(pin_);
+      pin_ = nullptr;
+      pin_bytes_ = 0;
+      if ((e = hipHostMalloc(&pin_, need, hipHostMallocDefault)) != hipSuccess) return ctx_->hip_fail(e, "engine staging");
+      pin_bytes_ = need;
     }
-    // reported f and relative error: fp64 evaluation at the best final point
-    double f64 = 0.0;
-    symtd_status s = final_fp64<T>(ctx_, st_, I->g.V, I->ld, I->g.nu, I->n, I->p, B.A_t, I->ld, B.lam_t, I->r,
-                                   I->pb.d, I->alpha, &f64);
-    if (s != SYMTD_OK) return s;
-    out->f = f64;
-    out->alpha = I->alpha;
-    out->rel_err = I->alpha > 0.0 ? std::sqrt(std::max(out->f, 0.0) / I->alpha) : NAN;
-    out->iters = hs[best].iters;
-    out->evals = hs[best].evals;
-    out->exit_reason = hs[best].reason;
-    out->best_restart = best;
-    out->steps = steps_;
+    if (set.size() > fdev_cap_) {
+      if (fdev_) (void)hipFree(fdev_);   // the previous collection waited for its use
+      fdev_ = nullptr;
+      fdev_cap_ = 0;
+      if ((e = hipMalloc(&fdev_, sizeof(double) * set.size())) != hipSuccess) {
+        (void)hipGetLastError();
+        return ctx_->fail(SYMTD_ENOMEM, "engine result buffer");
+      }
+      fdev_cap_ = set.size();
+    }
+    LbState* hs = (LbState*)pin_;
+    double* fh = (double*)((char*)pin_ + nst * sizeof(LbState));
+    size_t off = 0;
+    for (auto* I : set) {
+      if ((e = hipMemcpyAsync(hs + off, I->states, sizeof(LbState) * I->R, hipMemcpyDeviceToHost, st_)) != hipSuccess)
+        return ctx_->hip_fail(e, "engine collect");
+      off += (size_t)I->R;
+    }
+    if ((e = hipStreamSynchronize(st_)) != hipSuccess) return ctx_->hip_fail(e, "engine collect");
+    const hipMemcpyKind kind = host_outputs ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    off = 0;
+    for (size_t q = 0; q < set.size(); ++q) {
+      EngineInst<T>* I = set[q];
+      symtd_solve_result* out = outs[q];
+      const LbState* H = hs + off;
+      off += (size_t)I->R;
+      int best = 0;
+      for (int k = 1; k < I->R; ++k)
+        if (H[k].f < H[best].f || (std::isnan(H[best].f) && !std::isnan(H[k].f))) best = k;
+      const LbLane<T>& B = I->lanes[best];
+      if ((e = hipMemcpy2DAsync(out->A, (size_t)out->lda * sizeof(T), B.A_t, (size_t)I->ld * sizeof(T),
+                                (size_t)I->n * sizeof(T), (size_t)I->r, kind, st_)) != hipSuccess ||
+          (e = hipMemcpyAsync(out->lambda, B.lam_t, sizeof(double) * I->r, kind, st_)) != hipSuccess)
+        return ctx_->hip_fail(e, "engine result copy");
+      if (out->f_trace && I->trace_len > 0 &&
+          (e = hipMemcpyAsync(out->f_trace, I->trace, sizeof(double) * I->R * I->trace_len, hipMemcpyDeviceToHost,
+                              st_)) != hipSuccess)
+        return ctx_->hip_fail(e, "engine trace copy");
+      for (int k = 0; k < I->R; ++k) {
+        if (out->f_restarts) out->f_restarts[k] = H[k].f * I->scale;
+        if (out->iters_restarts) out->iters_restarts[k] = H[k].iters;
+        if (out->evals_restarts) out->evals_restarts[k] = H[k].evals;
+        if (out->exit_restarts) out->exit_restarts[k] = H[k].reason;
+      }
+      // reported f and relative error: fp64 evaluation at the best final point
+      symtd_status s = final_fp64_enqueue<T>(ctx_, st_, I->g.V, I->ld, I->g.nu, I->n, I->p, B.A_t, I->ld, B.lam_t,
+                                             I->r, I->pb.d, I->alpha, fdev_ + q);
+      if (s != SYMTD_OK) return s;
+      out->alpha = I->alpha;
+      out->iters = H[best].iters;
+      out->evals = H[best].evals;
+      out->exit_reason = H[best].reason;
+      out->best_restart = best;
+      out->steps = steps_;
+    }
+    if ((e = hipMemcpyAsync(fh, fdev_, sizeof(double) * set.size(), hipMemcpyDeviceToHost, st_)) != hipSuccess ||
+        (e = hipStreamSynchronize(st_)) != hipSuccess)
+      return ctx_->hip_fail(e, "engine collect sync");
+    for (size_t q = 0; q < set.size(); ++q) {
+      symtd_solve_result* out = outs[q];
+      const double a = set[q]->alpha;
+      out->f = fh[q];
+      out->rel_err = a > 0.0 ? std::sqrt(std::max(out->f, 0.0) / a) : NAN;
+    }
     return SYMTD_OK;
+  }
+
+  symtd_status collect(EngineInst<T>* I, symtd_solve_result* out, bool host_outputs) {
+    return collect_many(std::vector<EngineInst<T>*>{I}, std::vector<symtd_solve_result*>{out}, host_outputs);
   }
 
   // Remove a finished (or cancelled) instance and free its memory.
@@ -538,6 +585,9 @@ class GroupEngine {
     drop_graph();
     if (tab_) (void)hipFree(tab_);
     if (host_) (void)hipHostFree(host_);
+    if (pin_) (void)hipHostFree(pin_);
+    if (fdev_) (void)hipFree(fdev_);
+    pin_ = nullptr; fdev_ = nullptr; pin_bytes_ = 0; fdev_cap_ = 0;
     if (ev_) (void)hipEventDestroy(ev_);
     if (st_) (void)hipStreamDestroy(st_);
     tab_ = nullptr; host_ = nullptr; ev_ = nullptr; st_ = nullptr;
@@ -547,6 +597,10 @@ class GroupEngine {
   hipStream_t st_ = nullptr;
   hipEvent_t ev_ = nullptr;
   int* host_ = nullptr;
+  void* pin_ = nullptr;            // pinned staging of collected lane states and f values
+  size_t pin_bytes_ = 0;
+  double* fdev_ = nullptr;         // device f values of the instances being collected
+  size_t fdev_cap_ = 0;
   Arena arena_;
   bool use_graph_ = true, dirty_ = true;
   std::vector<EngineInst<T>*> live_;

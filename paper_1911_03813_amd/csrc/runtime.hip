@@ -320,9 +320,9 @@ template symtd_status run_rrf<double>(symtd_ctx*, hipStream_t, const double*, in
                                       int, uint64_t, const LbLane<double>*);
 
 template <typename T>
-symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
-                        int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d, double alpha,
-                        double* f_out, const Correction* corr) {
+symtd_status final_fp64_enqueue(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
+                                int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d,
+                                double alpha, double* f_dev, const Correction* corr) {
   // scratch: [V64 n x p][A64 n x r][G64 n x r][g r][f 1][correction terms r]
   auto plan = [&](Carve& c, double** V64, double** A64, double** G64, double** g, double** f, double** lc) {
     *V64 = std::is_same<T, float>::value ? c.take<double>((size_t)n * p) : nullptr;
@@ -350,6 +350,7 @@ symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv,
   }
   Carve c(ctx->wide);
   plan(c, &V64, &A64, &G64, &g, &fd, &lc);
+  if (f_dev) fd = f_dev;
   symtd_status s;
   if constexpr (std::is_same<T, float>::value) {
     launch_widen(st, V, ldv, V64, n, n, p);
@@ -361,12 +362,31 @@ symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv,
     if (s == SYMTD_OK && corr) launch_correction<double>(st, *corr, A, lda, (int)n, (int)r, 1, lambda, fd, g, G64, n, lc);
   }
   if (s != SYMTD_OK) return s;
-  if ((e = hipMemcpyAsync(&ctx->fwide_host, fd, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+  if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "final fp64 evaluation");
+  if (!f_dev) ctx->wide_f = fd;
+  return SYMTD_OK;
+}
+
+template <typename T>
+symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
+                        int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d, double alpha,
+                        double* f_out, const Correction* corr) {
+  symtd_status s = final_fp64_enqueue<T>(ctx, st, V, ldv, nu, n, p, A, lda, lambda, r, d, alpha, nullptr, corr);
+  if (s != SYMTD_OK) return s;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(&ctx->fwide_host, ctx->wide_f, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return ctx->hip_fail(e, "final fp64 evaluation");
   *f_out = ctx->fwide_host;
   return SYMTD_OK;
 }
+
+template symtd_status final_fp64_enqueue<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t,
+                                                int64_t, const float*, int64_t, const double*, int64_t, int, double,
+                                                double*, const Correction*);
+template symtd_status final_fp64_enqueue<double>(symtd_ctx*, hipStream_t, const double*, int64_t, const double*,
+                                                 int64_t, int64_t, const double*, int64_t, const double*, int64_t, int,
+                                                 double, double*, const Correction*);
 
 template symtd_status final_fp64<float>(symtd_ctx*, hipStream_t, const float*, int64_t, const double*, int64_t, int64_t,
                                         const float*, int64_t, const double*, int64_t, int, double, double*,

@@ -23,6 +23,7 @@ struct symtd_ctx {
   void* noalloc_ws = nullptr;   // this device's fixed scratch array (symtd_fg_noalloc)
   int* host_flag = nullptr;   // pinned host word for polling the solver's stop count
   double fwide_host = 0.0;    // host landing of the final fp64 evaluation
+  double* wide_f = nullptr;   // its device word in the scratch `wide`
   // hand-off flags of the split products (tagged with a launch epoch), and
   // the arrival counters of the closing step, one per model (zero between
   // launches)
@@ -125,6 +126,13 @@ template <typename T>
 symtd_status final_fp64(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
                         int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d, double alpha,
                         double* f_out, const Correction* corr = nullptr);
+// The same evaluation enqueued on `st` without waiting: f goes to the device
+// word f_dev.  Evaluations enqueued one after another on one stream share the
+// context's scratch in stream order.
+template <typename T>
+symtd_status final_fp64_enqueue(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, const double* nu, int64_t n,
+                                int64_t p, const T* A, int64_t lda, const double* lambda, int64_t r, int d,
+                                double alpha, double* f_dev, const Correction* corr = nullptr);
 
 // noise correction (corrected.hpp): the data's statistics m (and M2, when
 // not null) in fp64, and alpha_c = ||X - Delta||^2 from alpha = ||X||^2

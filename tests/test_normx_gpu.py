@@ -51,3 +51,17 @@ def test_normx_duplicated_columns(ctx):
     a1 = gpu_alpha(ctx, V, nu, 3, "f64")
     a2 = gpu_alpha(ctx, np.hstack([V, V]), np.concatenate([nu, nu]) / 2, 3, "f64")
     assert a2 == pytest.approx(a1, rel=1e-12)
+
+
+def test_normx_full_shape(ctx):
+    # the benchmark's data set (d=3, n=1000, p=1e5, fp32 storage) against the
+    # oracle's value stored by tests/golden/make_normx_full.py
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "normx_gmm_n1000_p1e5_d3.json")) as fh:
+        g = json.load(fh)
+    w = g["workload"]
+    print(f"case normx full shape n={w['n']} p={w['p']} d={w['d']}", flush=True)
+    V, nu, _ = synth.gmm(w["n"], w["r"], w["p"], w["sigma"], w["synth_key"])
+    got = gpu_alpha(ctx, V, nu, w["d"], "f32")
+    assert abs(got - g["value"]) <= 1e-12 * g["scale_abs"], (got, g["value"])

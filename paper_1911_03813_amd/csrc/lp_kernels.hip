@@ -455,6 +455,229 @@ __global__ __launch_bounds__(256) void k_lp_gemm1(LpG1Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// gemm1 with the observations streamed straight into registers
+// (k_lp_gemm1v): the same product, stream-K split, hand-off and epilogue as
+// k_lp_gemm1, but a wave's own observation rows never pass through LDS.  A
+// lane loads its 16-byte fragments (8 covariates of one observation, unit
+// 4 jg + g of the chunk, for both of its M subtiles) into a ring of
+// LP_VRING chunks, LP_VRING - 1 units ahead of the one being multiplied, so
+// that several chunks of V are in flight per wave; only the factor copy,
+// which all four waves share, is staged in LDS (two stages, loaded through
+// registers after the chunk's multiplies).  The compiler places every wait.
+// ---------------------------------------------------------------------------
+constexpr int LP_VRING = 4;
+
+template <int KIND, int NT>
+__global__ __launch_bounds__(256) void k_lp_gemm1v(LpG1Args a) {
+  using S = LpStage<KIND, NT>;
+  using E = typename LpT<KIND>::E;
+  constexpr int PL = S::PL;
+  constexpr int KCH = lp_chunk(KIND);
+  constexpr int J = S::U / 4;                    // 32-deep k steps per chunk
+  constexpr int PART = LP_WAVES * LP_MT * NT * 256;
+  constexpr int YPU = 16 * NT * S::U;            // factor units per plane and chunk
+  __shared__ u4 ly0[S::YP * 256], ly1[S::YP * 256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t B = a.nblocks, blk = blockIdx.x;
+  const int64_t KC = a.kc_len / KCH;
+  const int64_t U = (int64_t)a.nslab * KC;
+  const int64_t u0 = blk * U / B, u1 = (blk + 1) * U / B;
+  const E* V = (const E*)a.Vc;
+  const E* Ac = (const E*)a.Ac;
+  const int dm1 = a.d - 1;
+  const int epoch = handoff_epoch(a.ho.epoch);
+
+  f4 acc[LP_MT][NT];
+#pragma unroll
+  for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
+  double wsum[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) wsum[t] = 0.0;
+
+  // V fragments of one unit: [m][jg][plane]
+  u4 vr0[LP_MT][J][PL], vr1[LP_MT][J][PL], vr2[LP_MT][J][PL], vr3[LP_MT][J][PL];
+  static_assert(LP_VRING == 4, "four ring slots below");
+  auto vissue = [&](u4 (&vr)[LP_MT][J][PL], int64_t u) {
+    u = u < u1 ? u : u1 - 1;                     // past the block's range: repeat its last unit (unused)
+    const int64_t sl = u / KC, kc = u - sl * KC;
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m) {
+      int64_t l = (int64_t)LP_SLAB * sl + 16 * (LP_MT * wave + m) + c;
+      l = l < a.p ? l : (int64_t)a.p - 1;        // observations past p: weight 0
+      const E* col = V + l * a.ldc + kc * KCH + 8 * g;
+#pragma unroll
+      for (int jg = 0; jg < J; ++jg)
+#pragma unroll
+        for (int pl = 0; pl < PL; ++pl) vr[m][jg][pl] = gload(reinterpret_cast<const u4*>(col + pl * a.vplane + 32 * jg));
+    }
+  };
+  // factor units of one chunk: slot P of a stage holds unit unswz(P)
+  u4 ra[S::YP];
+  auto aload = [&](int64_t kc) {
+    const int64_t k0 = kc * KCH;
+#pragma unroll
+    for (int i = 0; i < S::YP; ++i) {
+      const int P = tid + 256 * i;
+      const int PP = P < S::YU ? P : 0;
+      const int pl = PP / YPU;
+      int col, q;
+      S::unswz(PP % YPU, col, q);
+      ra[i] = gload(reinterpret_cast<const u4*>(Ac + pl * a.aplane + (int64_t)(a.col0 + col) * a.ldc + k0 + 8 * q));
+    }
+  };
+  auto astore = [&](u4* ly) {
+#pragma unroll
+    for (int i = 0; i < S::YP; ++i) {
+      const int P = tid + 256 * i;
+      if (P < S::YU) ly[P] = ra[i];
+    }
+  };
+  auto compute = [&](const u4 (&vr)[LP_MT][J][PL], const u4* ly) {
+    u4 fa[2][NT][PL];
+    auto frag = [&](int b, int jg) {
+      const int q = 4 * jg + g;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int pl = 0; pl < PL; ++pl) fa[b][t][pl] = ly[pl * YPU + S::swz(16 * t + c, q)];
+    };
+    frag(0, 0);
+#pragma unroll
+    for (int jg = 0; jg < J; ++jg) {
+      if (jg + 1 < J) frag((jg + 1) & 1, jg + 1);
+#pragma unroll
+      for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = LpT<KIND>::mac(vr[m][jg], fa[jg & 1][t], acc[m][t]);
+    }
+  };
+
+  double nl[LP_MT][4];
+  auto load_nu = [&](int64_t sl) {
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t l = (int64_t)LP_SLAB * sl + 16 * (LP_MT * wave + m) + 4 * g + v;
+        nl[m][v] = a.nu[l < a.p ? l : (int64_t)a.p - 1];
+      }
+  };
+
+  auto finish_slab = [&](int64_t sl, int64_t kb, int64_t ke) {
+      if (kb > 0) {
+        float* pp = a.part + blk * PART + (int64_t)wave * (LP_MT * NT * 256);
+#pragma unroll
+        for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            xput4(pp + ((m * NT + t) * 64 + lane) * 4, acc[m][t]);
+        xput_complete();
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(a.ho.flag + blk, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (ke < KC) {
+          xwait_flag(a.ho.flag + blk + 1, (a.ho.spin >> 31) ? (epoch | 0x40000000) : epoch, a.ho.err,
+                     (int)(a.ho.spin & 0x7fffffffu));
+          const float* pp = a.part + (blk + 1) * PART + (int64_t)wave * (LP_MT * NT * 256);
+#pragma unroll
+          for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] += xget4v(pp + ((m * NT + t) * 64 + lane) * 4);
+          __syncthreads();
+          if (tid == 0) __hip_atomic_store(a.ho.flag + blk + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        f4 zp[LP_MT][NT];
+#pragma unroll
+        for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) zp[m][t] = f4{1.0f, 1.0f, 1.0f, 1.0f};
+        for (int e = 0; e < dm1; ++e)
+#pragma unroll
+          for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) zp[m][t] *= acc[m][t];
+        const float ws = (float)a.wscale;
+#pragma unroll
+        for (int m = 0; m < LP_MT; ++m) {
+          const int64_t lb = (int64_t)LP_SLAB * sl + 16 * (LP_MT * wave + m) + 4 * g;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            E out[PL][4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float wv = (lb + v < a.p ? (float)nl[m][v] : 0.0f) * zp[m][t][v];
+              wsum[t] += (double)wv * (double)acc[m][t][v];
+              E parts[PL];
+              LpT<KIND>::split(ws * wv, parts);
+#pragma unroll
+              for (int pl = 0; pl < PL; ++pl) out[pl][v] = parts[pl];
+            }
+            const int64_t col = a.col0 + 16 * t + c;
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl) {
+              E* dst = (E*)a.W + pl * a.wplane + ((lb >> 3) * a.rp + col) * 8 + (lb & 7);
+              uint2 packed;
+              __builtin_memcpy(&packed, out[pl], sizeof(packed));
+              *reinterpret_cast<uint2*>(dst) = packed;
+            }
+          }
+        }
+      }
+#pragma unroll
+    for (int m = 0; m < LP_MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = f4{0, 0, 0, 0};
+  };
+
+  if (u0 < u1) {
+    int64_t sl = u0 / KC, kc = u0 - sl * KC;
+    int64_t kb = kc;
+    // prologue: the factor chunk of the first unit in stage 0, V of the first three units
+    aload(kc);
+    vissue(vr0, u0);
+    vissue(vr1, u0 + 1);
+    vissue(vr2, u0 + 2);
+    astore(ly0);
+    __syncthreads();
+    // one unit: its V in ring slot SLOT, its factor chunk in stage SLOT mod 2
+    auto step = [&](int64_t u, u4 (&vcur)[LP_MT][J][PL], u4 (&vnext)[LP_MT][J][PL], u4* lcur, u4* lnext) {
+      if (kc == 0) load_nu(sl);
+      const bool more = u + 1 < u1;
+      const int64_t nsl = kc + 1 == KC ? sl + 1 : sl, nkc = kc + 1 == KC ? 0 : kc + 1;
+      if (more) aload(nkc);
+      vissue(vnext, u + LP_VRING - 1);
+      compute(vcur, lcur);
+      if (more) astore(lnext);
+      if (kc == KC - 1 || !more) {
+        finish_slab(sl, kb, kc + 1);
+        kb = 0;
+      }
+      __syncthreads();   // the next stage is written everywhere; this one is read
+      sl = nsl;
+      kc = nkc;
+    };
+    for (int64_t u = u0; u < u1; u += LP_VRING) {
+      step(u, vr0, vr3, ly0, ly1);
+      if (u + 1 < u1) step(u + 1, vr1, vr0, ly1, ly0);
+      if (u + 2 < u1) step(u + 2, vr2, vr1, ly0, ly1);
+      if (u + 3 < u1) step(u + 3, vr3, vr2, ly1, ly0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    double sm = wsum[t];
+    sm += __shfl_xor(sm, 16);
+    sm += __shfl_xor(sm, 32);
+    if (g == 0) a.wpart[(blk * LP_WAVES + wave) * (int64_t)a.rp + a.col0 + 16 * t + c] = sm;
+  }
+  handoff_done(a.ho.epoch, B, epoch);
+}
+
+// ---------------------------------------------------------------------------
 // gemm2: partial Y = V W over one split of the observations, one block per
 // (row slab, split), reading Vc; rows past n are zero in Vc and not read
 // ---------------------------------------------------------------------------
@@ -576,16 +799,24 @@ __global__ __launch_bounds__(256) void k_max_abs(const double* x, int64_t count,
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
+#ifndef SYMTD_LP_G1V
+#define SYMTD_LP_G1V 1
+#endif
+template <int KIND, int NT>
+void g1n(dim3 grid, hipStream_t st, const LpG1Args& a) {
+  if (SYMTD_LP_G1V) hipLaunchKernelGGL((k_lp_gemm1v<KIND, NT>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_lp_gemm1<KIND, NT>), grid, dim3(256), 0, st, a);
+}
 template <int KIND>
 void g1(int nt, dim3 grid, hipStream_t st, const LpG1Args& a) {
   switch (nt) {
-    case 1: hipLaunchKernelGGL((k_lp_gemm1<KIND, 1>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_lp_gemm1<KIND, 2>), grid, dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_lp_gemm1<KIND, 3>), grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_lp_gemm1<KIND, 4>), grid, dim3(256), 0, st, a); break;
-    case 5: hipLaunchKernelGGL((k_lp_gemm1<KIND, 5>), grid, dim3(256), 0, st, a); break;
-    case 6: hipLaunchKernelGGL((k_lp_gemm1<KIND, 6>), grid, dim3(256), 0, st, a); break;
-    case 7: hipLaunchKernelGGL((k_lp_gemm1<KIND, 7>), grid, dim3(256), 0, st, a); break;
+    case 1: g1n<KIND, 1>(grid, st, a); break;
+    case 2: g1n<KIND, 2>(grid, st, a); break;
+    case 3: g1n<KIND, 3>(grid, st, a); break;
+    case 4: g1n<KIND, 4>(grid, st, a); break;
+    case 5: g1n<KIND, 5>(grid, st, a); break;
+    case 6: g1n<KIND, 6>(grid, st, a); break;
+    case 7: g1n<KIND, 7>(grid, st, a); break;
     default: break;
   }
 }

@@ -222,3 +222,40 @@ def test_correction_recovers_the_clean_moment(ctx, d):
     print(f"  d={d} relative distance to the clean moment: plain {err[0.0]:.3e} corrected {err[sigma]:.3e}",
           flush=True)
     assert err[sigma] < 0.25 * err[0.0]
+
+
+@pytest.mark.parametrize("d", [3, 4])
+@pytest.mark.parametrize("n,p,r", [(1, 1, 1), (4, 3, 2), (4096, 40, 2)])
+def test_corrected_edge_shapes(ctx, d, n, p, r):
+    # one covariate and one observation; the largest n the correction takes
+    V, nu, A, lam = make_case(n, p, r, d, (n, p, d), sigma=0.2)
+    sigma = 0.4
+    print(f"case corrected edge d={d} n={n} p={p} r={r}", flush=True)
+    Vd, nud = to_dev(V, torch.float64), to_dev(nu, torch.float64)
+    m, M2 = S.symtd_moment_stats(ctx, Vd, nud, second=(d == 4))
+    f, g, G = S.symtd_fg_corrected(ctx, Vd, nud, to_dev(A, torch.float64), to_dev(lam, torch.float64), d, sigma,
+                                   m, M2, alpha=0.5)
+    torch.cuda.synchronize()
+    m_o, M2_o = Cr.stats(V, nu)
+    ref = Cr.fg_corrected(V, nu, A, lam, d, sigma, 0.5, m_o, M2_o)
+    mag = magnitudes(V, nu, A, lam, d, 0.5)
+    fa, pa = corr_scales(A, m_o, M2_o, sigma, d)
+    assert abs(float(f.cpu()[0]) - ref.f) <= 1e-12 * (mag.f_scale + 2 * float(np.abs(lam) @ fa))
+    assert np.all(np.abs(g.cpu().numpy() - ref.g_lambda) <= 1e-12 * (mag.g_scale + 2 * fa))
+    G_scale = mag.G_scale + 2 * d * np.abs(lam) * pa.max(axis=0)
+    assert np.all(np.abs(G.cpu().numpy() - ref.G_A) <= 1e-12 * G_scale[None, :])
+    alpha = normx_implicit(V, nu, d)
+    got = S.symtd_alpha_corrected(ctx, Vd, nud, d, sigma, m, M2, alpha)
+    want = Cr.alpha_corrected(V, nu, d, sigma, alpha, m_o, M2_o)
+    fv, _ = corr_scales(V, m_o, M2_o, sigma, d)
+    assert abs(got - want) <= 1e-12 * (alpha + 2 * float(nu @ fv) + Cr.delta_norm2(m_o, M2_o, sigma, d))
+
+
+def test_corrected_refuses_large_n(ctx):
+    V, nu, A, lam = make_case(4097, 8, 1, 3, (77,))
+    Vd, nud = to_dev(V, torch.float64), to_dev(nu, torch.float64)
+    m, _ = S.symtd_moment_stats(ctx, Vd, nud, second=False)
+    with pytest.raises(S.SymtdError):
+        S.symtd_fg_corrected(ctx, Vd, nud, to_dev(A, torch.float64), to_dev(lam, torch.float64), 3, 0.1, m, None)
+    with pytest.raises(S.SymtdError):
+        S.symtd_solve(ctx, Vd, nud, 3, 1, sigma=0.1)

@@ -311,16 +311,20 @@ class GroupEngine {
     }
     hipError_t e;
     if (use_graph_) {
+      // the K steps between two polls are one captured graph, so that only
+      // one launch boundary separates the polls (consecutive launches of a
+      // one-step graph leave a gap of several microseconds between steps)
+      if (exec_ && graph_steps_ != K) drop_graph();
       if (!exec_) {
         if ((e = hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal)) != hipSuccess)
           return ctx_->hip_fail(e, "graph capture");
-        enqueue_step();
+        for (int k = 0; k < K; ++k) enqueue_step();
         if ((e = hipStreamEndCapture(st_, &graph_)) != hipSuccess) return ctx_->hip_fail(e, "graph capture end");
         if ((e = hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0)) != hipSuccess)
           return ctx_->hip_fail(e, "graph instantiate");
+        graph_steps_ = K;
       }
-      for (int k = 0; k < K; ++k)
-        if ((e = hipGraphLaunch(exec_, st_)) != hipSuccess) return ctx_->hip_fail(e, "graph launch");
+      if ((e = hipGraphLaunch(exec_, st_)) != hipSuccess) return ctx_->hip_fail(e, "graph launch");
     } else {
       for (int k = 0; k < K; ++k) enqueue_step();
       if ((e = hipGetLastError()) != hipSuccess) return ctx_->hip_fail(e, "engine step");
@@ -617,6 +621,7 @@ class GroupEngine {
   std::vector<int> lane_done_host_;
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;
+  int graph_steps_ = 0;           // evaluation steps in the captured graph
   int64_t steps_ = 0;
 };
 

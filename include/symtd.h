@@ -566,7 +566,8 @@ void symtd_tune_clear(void);
  * 3/4, 1} x compute units and second-product splits in {1/2, 1, 2, 4} x the
  * automatic count (median of three rounds of `reps` calls, after two
  * warm-up calls), put the fastest into the table and return it in *out (may
- * be NULL).  Arguments as in symtd_fg. */
+ * be NULL).  Arguments as in symtd_fg; allocates its own output buffers and
+ * restores the context's split settings (symtd_set_tuning) afterwards. */
 symtd_status symtd_autotune_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
                                const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
                                const double* lambda, int64_t r, int d, symtd_prec prec, int reps,
@@ -576,7 +577,9 @@ symtd_status symtd_autotune_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt, con
  * shape (n, p, d) with `cols` columns each (factors taken from V's first
  * columns) for second-product splits of 4, 8, 16, 32 and 64 blocks of 16
  * observations, put the fastest into the table and return it.  Allocates
- * its own buffers. */
+ * its own buffers.  While it runs, every grouped evaluation in the process
+ * (other threads and servers included) takes the candidate split being
+ * timed: tune before serving, not beside it. */
 symtd_status symtd_autotune_grouped(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
                                     const double* nu, int64_t n, int64_t p, int d, int64_t cols, int copies,
                                     int reps, symtd_tune_entry* out);

@@ -234,6 +234,33 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
       mfma(jg & 1);
     }
   };
+  // a slab's last chunk when n is not a whole number of chunks: only its
+  // first jlast 16-k groups reach covariates below n (the rest would
+  // multiply the factor copy's zero rows), so only those are multiplied
+  // (fp64; in fp32 the extra body costs the chunk loop registers)
+  constexpr int JG = QPC / 4;
+  const int jlast = (int)((n - (KC - 1) * KCH + 15) / 16);
+  auto compute_last = [&](const Quad<T>* lv, const Quad<T>* la) {
+    for (int jg = 0; jg < jlast; ++jg) {
+      const int q = 4 * jg + g;
+      Quad<T> fv[MT], fa[NT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) fv[m] = lv[swz(16 * (MT * wave + m) + c, q)];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) fa[t] = la[swz(16 * t + c, q)];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(fv[m].e[s], fa[t].e[s], acc[m][t]);
+    }
+  };
+  // chunk kc of a slab, through the shortened product when it is the ragged last one
+  auto compute_chunk = [&](const Quad<T>* lv, const Quad<T>* la, int64_t kc) {
+    if (sizeof(T) == 8 && kc == KC - 1 && jlast < JG) compute_last(lv, la);
+    else compute(lv, la);
+  };
   // wait until chunk kc (with `later` chunks issued after it) has landed, then
   // the block-wide barrier: everyone's pieces are in, and the stage read in the
   // previous step is free again
@@ -294,9 +321,9 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
             compute(lv0, la0);
             arrive(0);
             if (q + 2 < nk) dma(lv0, la0, sl, kb + q + 2);
-            compute(lv1, la1);
+            compute_chunk(lv1, la1, kb + q + 1);
           }
-          if (q < nk) { arrive(0); compute(lv0, la0); }
+          if (q < nk) { arrive(0); compute_chunk(lv0, la0, kb + q); }
         }
       } else {
         gload(sl, kb);

@@ -269,6 +269,27 @@ typedef struct symtd_solve_opts {
                                n <= 4096; see symtd_fg_corrected); alpha then stands for
                                ||X - Delta||^2 (computed, given or 0).  0 = the plain objective.
                                symtd_solve only (the batched and served forms refuse it) */
+  /* Checkpoint and resume (symtd_solve only; the batched and served forms
+   * refuse them).  The state of a solve between two evaluation steps is its
+   * restarts' L-BFGS vectors x, g, d, S, Y, their next trial points, their
+   * line-search and counter state, the stop counter and the f traces; it is
+   * written to and read from caller-owned host memory as one opaque block
+   * of symtd_solve_state_bytes bytes. */
+  int64_t pause_after;      /* > 0: once this many evaluation steps have run (counting those of
+                               the solve it resumes) while some restart is still running, write
+                               the state to state_out and return SYMTD_OK with exit_reason
+                               SYMTD_EXIT_RUNNING and steps = pause_after; A, lambda and the
+                               other figures of the result are not written.  0 = run to the end */
+  void* state_out;          /* host, symtd_solve_state_bytes bytes, written when the solve pauses;
+                               NULL = pause without saving */
+  const void* state_in;     /* host: a state written by a paused solve of the same problem and the
+                               same options (pause_after, state_out, state_in, A0 and check_every
+                               aside) and trace_len; the solve continues from it, taking its
+                               starts and alpha from it, and ends with the same results as an
+                               uninterrupted solve, bit for bit (steps aside: the steps that run
+                               after every restart has stopped depend on check_every).  A state
+                               of another problem or other options is refused with SYMTD_EINVAL
+                               (V and nu themselves are not checked).  NULL = start afresh */
 } symtd_solve_opts;
 
 typedef struct symtd_solve_result {
@@ -296,11 +317,20 @@ typedef struct symtd_solve_result {
 
 /* Fill `opts` with defaults: fp32 products, m = 5, pgtol = 1e-4, ftol =
  * 2.22e-9, max_iters = 10000, max_evals = 50000 (Section 4), 1 restart,
- * seed 0, RRF starts, alpha computed, no noise correction. */
+ * seed 0, RRF starts, alpha computed, no noise correction, no pause and
+ * no saved state. */
 symtd_status symtd_solve_opts_default(symtd_solve_opts* opts);
 
 symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb,
                          const symtd_solve_opts* opts, symtd_solve_result* out);
+
+/* Size in bytes of the state that symtd_solve writes when it pauses, for
+ * this problem, these options and a result with this trace_len (0 without
+ * a trace).  Host-only: needs no device.  SYMTD_EINVAL on a null argument,
+ * r < 1, restarts or m out of range, a negative trace_len or an unknown
+ * storage type. */
+symtd_status symtd_solve_state_bytes(const symtd_problem* pb, const symtd_solve_opts* opts, int64_t trace_len,
+                                     size_t* bytes);
 
 /* ------------------------------------------------------------------------
  * Moments corrected for spherical Gaussian noise (the lower-order terms that

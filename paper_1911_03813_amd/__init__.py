@@ -57,7 +57,8 @@ class SolveOpts(ctypes.Structure):
                 ("max_iters", ctypes.c_int64), ("max_evals", ctypes.c_int64), ("restarts", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("init", ctypes.c_int), ("alpha_mode", ctypes.c_int),
                 ("alpha", ctypes.c_double), ("A0", ctypes.c_void_p), ("check_every", ctypes.c_int),
-                ("sigma", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("pause_after", ctypes.c_int64), ("state_out", ctypes.c_void_p),
+                ("state_in", ctypes.c_void_p)]
 
 
 class FgItem(ctypes.Structure):
@@ -143,6 +144,7 @@ SIGNATURES = {
     "symtd_fg_data": (_int, [_vp, _vp, _vp, _vp, _i64, _vp, _i64, _int, _dbl, _vp, _vp, _vp, _i64]),
     "symtd_solve_opts_default": (_int, [_c.POINTER(SolveOpts)]),
     "symtd_solve": (_int, [_vp, _vp, _c.POINTER(Problem), _c.POINTER(SolveOpts), _c.POINTER(SolveResult)]),
+    "symtd_solve_state_bytes": (_int, [_c.POINTER(Problem), _c.POINTER(SolveOpts), _i64, _c.POINTER(_c.c_size_t)]),
     "symtd_form_moment": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _int, _vp]),
     "symtd_moment_stats": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _vp]),
     "symtd_fg_corrected": (_int, [_vp, _vp, _int, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _int, _dbl,
@@ -361,6 +363,7 @@ def symtd_fg_multi(ctx: Context, V, nu, A, lam, r: int, d: int, alpha: float = 0
 
 INIT_GAUSS, INIT_RRF = 0, 1
 ALPHA_COMPUTE, ALPHA_GIVEN, ALPHA_NONE = 0, 1, 2
+EXIT_RUNNING = 0
 EXIT_NAMES = {0: "RUNNING", 1: "PGTOL", 2: "FTOL", 3: "MAX_ITERS", 4: "MAX_EVALS", 5: "LINESEARCH", 6: "NONFINITE"}
 
 
@@ -369,7 +372,7 @@ class _SolveCall:
 
     def __init__(self, V, nu, d, r, prec=None, m=5, pgtol=1e-4, ftol=2.220446049250313e-09, max_iters=10000,
                  max_evals=50000, restarts=1, seed=0, init=None, alpha=None, A0=None, check_every=0,
-                 trace_len=0, sigma=0.0):
+                 trace_len=0, sigma=0.0, pause_after=0, state=None):
         import numpy as np
         import torch
         Vp, ldv = _mat(V, "V")
@@ -398,6 +401,17 @@ class _SolveCall:
             self.keep.append(A0)
         o.check_every = int(check_every)
         o.sigma = float(sigma)
+        o.pause_after = int(pause_after)
+        self.state_out = None
+        if pause_after > 0:
+            nbytes = ctypes.c_size_t()
+            _check(None, lib().symtd_solve_state_bytes(ctypes.byref(self.pb), ctypes.byref(o), int(trace_len),
+                                                       ctypes.byref(nbytes)))
+            self.state_out = ctypes.create_string_buffer(nbytes.value)
+            o.state_out = ctypes.cast(self.state_out, ctypes.c_void_p)
+        if state is not None:
+            self.state_in = ctypes.create_string_buffer(bytes(state), len(state))
+            o.state_in = ctypes.cast(self.state_in, ctypes.c_void_p)
         self.opts = o
         self.A = colmajor(torch.empty(n, r, dtype=V.dtype, device=V.device))
         self.lam = torch.empty(r, dtype=torch.float64, device=V.device)
@@ -424,24 +438,32 @@ class _SolveCall:
                 "iters": res.iters, "evals": res.evals, "exit_reason": res.exit_reason,
                 "best_restart": res.best_restart, "steps": res.steps, "f_restarts": self.fr,
                 "iters_restarts": self.ir, "evals_restarts": self.er, "exit_restarts": self.xr,
-                "f_trace": self.tr[:, :self.trace_len] if self.trace_len > 0 else None}
+                "f_trace": self.tr[:, :self.trace_len] if self.trace_len > 0 else None,
+                "paused": self.state_out is not None and res.exit_reason == EXIT_RUNNING,
+                "state": (self.state_out.raw if self.state_out is not None and res.exit_reason == EXIT_RUNNING
+                          else None)}
 
 
 def symtd_solve(ctx: Context, V, nu, d: int, r: int, *, prec: int | None = None, m: int = 5, pgtol: float = 1e-4,
                 ftol: float = 2.220446049250313e-09, max_iters: int = 10000, max_evals: int = 50000,
                 restarts: int = 1, seed: int = 0, init: int = INIT_RRF, alpha=None, A0=None,
-                check_every: int = 0, trace_len: int = 0, sigma: float = 0.0, stream=None):
+                check_every: int = 0, trace_len: int = 0, sigma: float = 0.0, pause_after: int = 0,
+                state: bytes | None = None, stream=None):
     """Restarted L-BFGS solve on the device (symtd_solve).
 
     alpha: None = compute ||X||^2 on the device, a positive number = use it,
     0 = shifted objective.  A0 (optional): n x (restarts*r) column-major
     device tensor of starts.  sigma > 0 (d = 3 or 4): fit the moment
     corrected for spherical Gaussian noise of that level; alpha then stands
-    for ||X - Delta||^2.  Returns a dict with the best model (A, lam as
-    device tensors) and the host figures of the solve.
+    for ||X - Delta||^2.  pause_after > 0: stop after that many evaluation
+    steps if a restart is still running; the dict then has paused = True and
+    the solver's state as bytes under "state", which `state` takes to
+    continue the same solve (same problem and options).  Returns a dict with
+    the best model (A, lam as device tensors) and the host figures of the
+    solve.
     """
     call = _SolveCall(V, nu, d, r, prec, m, pgtol, ftol, max_iters, max_evals, restarts, seed, init, alpha, A0,
-                      check_every, trace_len, sigma)
+                      check_every, trace_len, sigma, pause_after, state)
     _check(ctx, lib().symtd_solve(ctx.handle, _stream(stream), ctypes.byref(call.pb), ctypes.byref(call.opts),
                                   ctypes.byref(call.res)))
     return call.result()

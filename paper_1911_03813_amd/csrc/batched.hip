@@ -174,6 +174,8 @@ symtd_status symtd_solve_batched(symtd_ctx* ctx, void* stream, int64_t count, co
     if (s != SYMTD_OK) return ctx->fail(s, "problem %lld: %s", (long long)i, ctx->err.c_str());
     if (opts[i].sigma != 0.0)
       return ctx->fail(SYMTD_EINVAL, "problem %lld: the noise correction is symtd_solve's only", (long long)i);
+    if (opts[i].pause_after != 0 || opts[i].state_out || opts[i].state_in)
+      return ctx->fail(SYMTD_EINVAL, "problem %lld: pausing and resuming are symtd_solve's only", (long long)i);
     if (pbs[i].dt != pbs[0].dt) return ctx->fail(SYMTD_EINVAL, "problem %lld: all problems must share a dtype", (long long)i);
   }
   if (count == 0) return SYMTD_OK;

@@ -93,6 +93,8 @@ class Server final : public symtd_server {
     if (pb->dt != opts_.dt || o->prec != opts_.prec) return fail(SYMTD_EINVAL, "request dtype/precision differ from the server's");
     if (o->A0) return fail(SYMTD_EINVAL, "served requests draw their own starts (A0 must be NULL)");
     if (o->sigma != 0.0) return fail(SYMTD_EINVAL, "the noise correction is symtd_solve's only (sigma must be 0)");
+    if (o->pause_after != 0 || o->state_out || o->state_in)
+      return fail(SYMTD_EINVAL, "pausing and resuming are symtd_solve's only");
     symtd_solve_result dummy{};
     dummy.A = (void*)16; dummy.lambda = (double*)16; dummy.lda = pb->n;
     {

@@ -71,6 +71,40 @@ struct SolveLayout {
   }
 };
 
+// The saved state of a paused solve: a header, then the persistent device
+// arrays in a fixed order, each at an 8-byte aligned offset.  Everything
+// else on the device (the evaluation outputs, the dot partials, the
+// correction's per-column terms) is rewritten by every step before it is
+// read, and the lane descriptors follow from the problem and the options.
+struct StateHeader {
+  char magic[8];
+  int32_t version, dt, prec, d, R, m, nb, init, alpha_mode, pad;
+  int64_t n, p, r, N, trace_len, max_iters, max_evals, steps;
+  uint64_t seed;
+  double pgtol, ftol, sigma, alpha_given, alpha, scale;
+  uint64_t bytes;
+};
+constexpr char kStateMagic[8] = {'S', 'Y', 'M', 'T', 'D', 'S', 'T', '1'};
+
+struct StateLayout {
+  size_t x, g, dd, S, Y, lam, A, states, done, trace, bytes;
+  StateLayout(size_t esz, int64_t N, int64_t n, int64_t r, int R, int m, int64_t trace_len) {
+    size_t off = sizeof(StateHeader);
+    auto put = [&](size_t len) { off = (off + 7) & ~(size_t)7; const size_t at = off; off += len; return at; };
+    x = put(sizeof(double) * R * N);
+    g = put(sizeof(double) * R * N);
+    dd = put(sizeof(double) * R * N);
+    S = put(sizeof(double) * R * m * N);
+    Y = put(sizeof(double) * R * m * N);
+    lam = put(sizeof(double) * R * r);
+    A = put(esz * n * r * R);
+    states = put(sizeof(LbState) * R);
+    done = put(sizeof(int));
+    trace = put(sizeof(double) * R * trace_len);
+    bytes = (off + 7) & ~(size_t)7;
+  }
+};
+
 }  // namespace
 
 namespace symtd {
@@ -103,6 +137,7 @@ symtd_status check_solve(symtd_ctx* ctx, const symtd_problem* pb, const symtd_so
   if (!(o->sigma >= 0.0) || !std::isfinite(o->sigma)) return ctx->fail(SYMTD_EINVAL, "sigma must be finite and >= 0");
   if (o->sigma > 0.0 && ((pb->d != 3 && pb->d != 4) || pb->n > CORR_NMAX))
     return ctx->fail(SYMTD_EINVAL, "the noise correction is derived for d = 3 and d = 4 (n <= %d)", CORR_NMAX);
+  if (o->pause_after < 0) return ctx->fail(SYMTD_EINVAL, "pause_after < 0");
   return SYMTD_OK;
 }
 
@@ -134,9 +169,29 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
     if (e != hipSuccess) return ctx->hip_fail(e, "hipHostMalloc");
   }
 
+  // a saved state to continue from: it must come from this problem and these options
+  const StateLayout SL(sizeof(T), N, n, r, R, m, trace_len);
+  StateHeader H{};
+  if (o.state_in) {
+    std::memcpy(&H, o.state_in, sizeof(H));
+    const bool same = std::memcmp(H.magic, kStateMagic, 8) == 0 && H.version == 1 && H.dt == (int)pb.dt &&
+                      H.prec == (int)o.prec && H.d == d && H.R == R && H.m == m && H.nb == nb &&
+                      H.init == (int)o.init && H.alpha_mode == (int)o.alpha_mode && H.n == n && H.p == p &&
+                      H.r == r && H.N == N && H.trace_len == trace_len && H.max_iters == o.max_iters &&
+                      H.max_evals == o.max_evals && H.seed == o.seed && H.pgtol == o.pgtol && H.ftol == o.ftol &&
+                      H.sigma == o.sigma && H.alpha_given == (o.alpha_mode == SYMTD_ALPHA_GIVEN ? o.alpha : 0.0) &&
+                      H.bytes == SL.bytes;
+    if (!same) return ctx->fail(SYMTD_EINVAL, "the saved state belongs to another problem or other options");
+    if (o.pause_after > 0 && o.pause_after <= H.steps)
+      return ctx->fail(SYMTD_EINVAL, "pause_after=%lld is not past the %lld steps of the saved state",
+                       (long long)o.pause_after, (long long)H.steps);
+  }
+
   // alpha and the scale of the objective
   double alpha = 0.0;
-  if (o.alpha_mode == SYMTD_ALPHA_COMPUTE) {
+  if (o.state_in) {
+    alpha = H.alpha;
+  } else if (o.alpha_mode == SYMTD_ALPHA_COMPUTE) {
     if ((s = run_normx<T>(ctx, st, V, pb.ldv, pb.nu, n, p, d, Lay.alpha)) != SYMTD_OK) return s;
     if ((e = hipMemcpyAsync(&ctx->host_flag[2], Lay.alpha, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
@@ -150,13 +205,13 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
   const Correction corr{Lay.cm, Lay.cM2, o.sigma, d};
   if (Lay.corr) {
     launch_stats<T>(st, V, pb.ldv, pb.nu, n, p, Lay.cm, d == 4 ? Lay.cM2 : nullptr);
-    if (o.alpha_mode == SYMTD_ALPHA_COMPUTE) {
+    if (o.alpha_mode == SYMTD_ALPHA_COMPUTE && !o.state_in) {
       if ((s = corrected_alpha<T>(ctx, st, corr, V, pb.ldv, pb.nu, n, p, alpha, &alpha, Lay.cxd)) != SYMTD_OK) return s;
       if (!(alpha > 0.0 && std::isfinite(alpha)))
         return ctx->fail(SYMTD_ENONFINITE, "||X - Delta||^2 = %g is not positive", alpha);
     }
   }
-  const double scale = alpha > 0.0 ? alpha : 1.0;
+  const double scale = o.state_in ? H.scale : (alpha > 0.0 ? alpha : 1.0);
 
   // lane descriptors and zeroed state
   std::vector<LbLane<T>> lanes(R);
@@ -178,7 +233,23 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
     L.m = m; L.pgtol = o.pgtol; L.ftol = o.ftol; L.max_iters = o.max_iters; L.max_evals = o.max_evals;
   }
   const size_t vec_bytes = (size_t)R * N * sizeof(double);
-  if ((e = hipMemcpyAsync(Lay.lanes, lanes.data(), sizeof(LbLane<T>) * R, hipMemcpyHostToDevice, st)) != hipSuccess ||
+  // the persistent arrays and where the saved state keeps them
+  struct Part { void* dev; size_t off, len; };
+  const Part parts[] = {
+      {Lay.x, SL.x, vec_bytes}, {Lay.g, SL.g, vec_bytes}, {Lay.dd, SL.dd, vec_bytes},
+      {Lay.S, SL.S, vec_bytes * m}, {Lay.Y, SL.Y, vec_bytes * m}, {Lay.lam_t, SL.lam, sizeof(double) * R * r},
+      {Lay.A_t, SL.A, sizeof(T) * n * r * R}, {Lay.states, SL.states, sizeof(LbState) * R},
+      {Lay.done, SL.done, sizeof(int)}, {Lay.trace, SL.trace, sizeof(double) * R * trace_len}};
+  int64_t steps = 0;
+  if (o.state_in) {
+    if ((e = hipMemcpyAsync(Lay.lanes, lanes.data(), sizeof(LbLane<T>) * R, hipMemcpyHostToDevice, st)) != hipSuccess)
+      return ctx->hip_fail(e, "solver set-up");
+    for (const Part& q : parts)
+      if (q.len > 0 && (e = hipMemcpyAsync(q.dev, (const char*)o.state_in + q.off, q.len, hipMemcpyHostToDevice,
+                                           st)) != hipSuccess)
+        return ctx->hip_fail(e, "restoring the saved state");
+    steps = H.steps;
+  } else if ((e = hipMemcpyAsync(Lay.lanes, lanes.data(), sizeof(LbLane<T>) * R, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemsetAsync(Lay.g, 0, vec_bytes, st)) != hipSuccess ||
       (e = hipMemsetAsync(Lay.dd, 0, vec_bytes, st)) != hipSuccess ||
       (e = hipMemsetAsync(Lay.S, 0, vec_bytes * m, st)) != hipSuccess ||
@@ -188,8 +259,9 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
       (trace_len > 0 && (e = hipMemsetAsync(Lay.trace, 0xFF, sizeof(double) * R * trace_len, st)) != hipSuccess))
     return ctx->hip_fail(e, "solver set-up");
 
-  // starts
-  if (o.A0) {
+  // starts (a resumed solve has its points already)
+  if (o.state_in) {
+  } else if (o.A0) {
     launch_init_given<T>(nb, R, st, Lay.lanes);
   } else if (o.init == SYMTD_INIT_GAUSS) {
     launch_init_gauss<T>(nb, R, st, Lay.lanes);
@@ -203,11 +275,12 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
   // steps between polls: enough to keep the queue ahead of the device, few
   // enough that little work is done after the last lane has stopped
   const double work = 4.0 * (double)n * (double)p * (double)r * R;
-  int K = o.check_every > 0 ? o.check_every : (work > 1e9 ? 4 : work > 1e7 ? 16 : 64);
-  int64_t steps = 0;
+  const int K = o.check_every > 0 ? o.check_every : (work > 1e9 ? 4 : work > 1e7 ? 16 : 64);
   const int64_t step_cap = o.max_evals + 2;   // every running lane spends one evaluation per step
   while (true) {
-    for (int k = 0; k < K; ++k) {
+    // a pause falls on a poll
+    const int64_t Kr = o.pause_after > 0 ? std::min<int64_t>(K, o.pause_after - steps) : K;
+    for (int64_t k = 0; k < Kr; ++k) {
       if ((s = run_fg<T>(ctx, st, V, pb.ldv, pb.nu, n, p, Lay.A_t, n, Lay.lam_t, r, R, d, alpha, Lay.f_t, Lay.glam_t,
                          Lay.G_t, n)) != SYMTD_OK)
         return s;
@@ -225,6 +298,28 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
       return ctx->hip_fail(e, "polling the solver");
     if ((s = ctx->take_device_error()) != SYMTD_OK) return s;
     if (ctx->host_flag[0] >= R) break;
+    if (o.pause_after > 0 && steps >= o.pause_after) {
+      // pause: save the state between two steps
+      if (o.state_out) {
+        StateHeader W{};
+        std::memcpy(W.magic, kStateMagic, 8);
+        W.version = 1; W.dt = (int)pb.dt; W.prec = (int)o.prec; W.d = d; W.R = R; W.m = m; W.nb = nb;
+        W.init = (int)o.init; W.alpha_mode = (int)o.alpha_mode;
+        W.n = n; W.p = p; W.r = r; W.N = N; W.trace_len = trace_len; W.max_iters = o.max_iters;
+        W.max_evals = o.max_evals; W.steps = steps; W.seed = o.seed; W.pgtol = o.pgtol; W.ftol = o.ftol;
+        W.sigma = o.sigma; W.alpha_given = o.alpha_mode == SYMTD_ALPHA_GIVEN ? o.alpha : 0.0;
+        W.alpha = alpha; W.scale = scale; W.bytes = SL.bytes;
+        for (const Part& q : parts)
+          if (q.len > 0 && (e = hipMemcpyAsync((char*)o.state_out + q.off, q.dev, q.len, hipMemcpyDeviceToHost,
+                                               st)) != hipSuccess)
+            return ctx->hip_fail(e, "saving the state");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return ctx->hip_fail(e, "saving the state");
+        std::memcpy(o.state_out, &W, sizeof(W));
+      }
+      out->exit_reason = SYMTD_EXIT_RUNNING;
+      out->steps = steps;
+      return SYMTD_OK;
+    }
     if (steps > step_cap) return ctx->fail(SYMTD_EDEVICE, "solver did not stop within %lld steps", (long long)steps);
   }
 
@@ -288,6 +383,19 @@ symtd_status symtd_solve_opts_default(symtd_solve_opts* o) {
   o->A0 = nullptr;
   o->check_every = 0;
   o->sigma = 0.0;
+  o->pause_after = 0;
+  o->state_out = nullptr;
+  o->state_in = nullptr;
+  return SYMTD_OK;
+}
+
+symtd_status symtd_solve_state_bytes(const symtd_problem* pb, const symtd_solve_opts* o, int64_t trace_len,
+                                     size_t* bytes) {
+  if (!pb || !o || !bytes || pb->r < 1 || pb->n < 1 || o->restarts < 1 || o->restarts > 4096 || o->m < 1 ||
+      o->m > LB_MMAX || trace_len < 0 || (pb->dt != SYMTD_F64 && pb->dt != SYMTD_F32))
+    return SYMTD_EINVAL;
+  const int64_t N = pb->r + pb->n * pb->r;
+  *bytes = StateLayout(pb->dt == SYMTD_F64 ? 8 : 4, N, pb->n, pb->r, o->restarts, o->m, trace_len).bytes;
   return SYMTD_OK;
 }
 

@@ -68,7 +68,8 @@ def test_struct_layouts_match_header(tmp_path):
     checks = {
         "symtd_problem": (S.Problem, ["dt", "V", "ldv", "nu", "n", "p", "d", "r"]),
         "symtd_solve_opts": (S.SolveOpts, ["prec", "m", "pgtol", "ftol", "max_iters", "max_evals", "restarts",
-                                           "seed", "init", "alpha_mode", "alpha", "A0", "check_every", "sigma"]),
+                                           "seed", "init", "alpha_mode", "alpha", "A0", "check_every", "sigma",
+                                           "pause_after", "state_out", "state_in"]),
         "symtd_fg_item": (S.FgItem, ["V", "ldv", "nu", "n", "p", "d", "A", "lda", "lambda", "r", "models",
                                      "alpha", "f", "g_lambda", "G_A", "ldg"]),
         "symtd_adam_opts": (S.AdamOpts, ["prec", "samples", "est_samples", "epoch_len", "max_epochs", "lr0",
@@ -104,3 +105,30 @@ def test_struct_layouts_match_header(tmp_path):
             assert fld_py in names, (cname, fld)
             want.append(getattr(cls, fld_py).offset)
     assert got == want
+
+
+def test_solve_state_bytes():
+    # the size of a paused solve's state: host-only, so it runs without a GPU
+    import ctypes
+
+    def size(dt=0, n=30, r=4, restarts=3, m=5, trace_len=0):
+        pb = S.Problem(dt, None, n, None, n, 1000, 3, r)
+        o = S.SolveOpts()
+        assert S.lib().symtd_solve_opts_default(ctypes.byref(o)) == 0
+        o.restarts, o.m = restarts, m
+        out = ctypes.c_size_t()
+        st = S.lib().symtd_solve_state_bytes(ctypes.byref(pb), ctypes.byref(o), trace_len, ctypes.byref(out))
+        return st, out.value
+
+    st, base = size()
+    assert st == 0
+    N = 4 + 30 * 4
+    # x, g, d and m pairs of S, Y per restart; fp64 trial factors; per-restart state
+    assert base >= 3 * (3 + 2 * 5) * N * 8 + 3 * 4 * 8 + 30 * 4 * 3 * 8
+    assert size(m=6)[1] == base + 2 * 3 * N * 8
+    assert size(trace_len=10)[1] == base + 3 * 10 * 8
+    assert size(dt=1)[1] == base - 30 * 4 * 3 * 4
+    assert size(restarts=4)[1] > base
+    for bad in (dict(r=0), dict(restarts=0), dict(restarts=4097), dict(m=0), dict(m=9), dict(trace_len=-1),
+                dict(dt=7)):
+        assert size(**bad)[0] == -1, bad

@@ -23,6 +23,7 @@ LIB = os.path.join(PKG, "libsymtd.so")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = "/opt/rocm/lib"
 
 CFLAGS = [
     f"--offload-arch={ARCH}",
@@ -61,7 +62,9 @@ def build(verbose: bool = False, resource: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, resource), srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    # roctx: the solve, step and admission ranges that rocprofv3 --marker-trace records
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-L", ROCM_LIB,
+           "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         print(res.stdout + res.stderr, file=sys.stderr)

@@ -182,6 +182,7 @@ symtd_status symtd_solve_batched(symtd_ctx* ctx, void* stream, int64_t count, co
   symtd_status s = ctx->set_device();
   if (s != SYMTD_OK) return s;
   hipStream_t st = (hipStream_t)stream;
+  Marker mk("symtd_solve_batched");
   if (pbs[0].dt == SYMTD_F64) s = run_solve_batched<double>(ctx, st, count, pbs, opts, outs);
   else s = run_solve_batched<float>(ctx, st, count, pbs, opts, outs);
   if (s != SYMTD_OK) return s;

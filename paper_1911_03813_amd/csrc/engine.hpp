@@ -303,6 +303,7 @@ class GroupEngine {
   // K evaluation steps of every live instance
   symtd_status run(int K) {
     if (live_.empty()) return SYMTD_OK;
+    Marker mk("grouped steps");
     symtd_status s;
     if (dirty_) {
       if ((s = upload(live_, false)) != SYMTD_OK) return s;

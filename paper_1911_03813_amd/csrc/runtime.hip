@@ -654,6 +654,7 @@ symtd_status symtd_fg_multi(symtd_ctx* ctx, void* stream, symtd_dtype dt, const 
                             const double* nu, int64_t n, int64_t p, const void* A, int64_t lda,
                             const double* lambda, int64_t r, int64_t models, int d, double alpha, symtd_prec prec,
                             double* f, double* g_lambda, void* G_A, int64_t ldg) {
+  Marker mk("symtd_fg");
   return fg_multi_impl(ctx, stream, dt, V, ldv, nu, n, p, A, lda, lambda, r, models, d, alpha, prec, f, g_lambda,
                        G_A, ldg, nullptr, 0);
 }
@@ -671,6 +672,7 @@ symtd_status symtd_fg_noalloc(symtd_ctx* ctx, void* stream, symtd_dtype dt, cons
 symtd_status symtd_normX(symtd_ctx* ctx, void* stream, symtd_dtype dt, const void* V, int64_t ldv,
                          const double* nu, int64_t n, int64_t p, int d, double* alpha) {
   if (!ctx) return SYMTD_EINVAL;
+  Marker mk("symtd_normX");
   ctx->err.clear();
   symtd_status s = ctx->take_device_error();
   if (s != SYMTD_OK) return s;

@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "corrected.hpp"
 #include "kernels.hpp"
 #include "symtd.h"
@@ -66,6 +68,16 @@ struct symtd_ctx {
 };
 
 namespace symtd {
+
+// A roctx range over a host-side scope (a solve, a batch of steps, an
+// admission): rocprofv3 --marker-trace records it beside the kernels the
+// scope enqueued; without a profiler attached the calls do nothing.
+struct Marker {
+  explicit Marker(const char* what) { roctxRangePushA(what); }
+  ~Marker() { roctxRangePop(); }
+  Marker(const Marker&) = delete;
+  Marker& operator=(const Marker&) = delete;
+};
 
 // Launch shape and workspace of one evaluation (the products' splits and the
 // element counts of the workspace buffers), from the sizes alone.

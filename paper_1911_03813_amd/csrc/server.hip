@@ -239,6 +239,7 @@ class Server final : public symtd_server {
           rq->t_admit = now();
           batch.push_back(rq->inst.get());
         }
+        Marker mk("server admission");
         s = eng_->admit(batch);
         if (s == SYMTD_EREJECTED) {
           // the free memory was too fragmented: back to the head of the queue

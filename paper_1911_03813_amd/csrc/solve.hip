@@ -280,6 +280,7 @@ symtd_status run_solve(symtd_ctx* ctx, hipStream_t st, const symtd_problem& pb, 
   while (true) {
     // a pause falls on a poll
     const int64_t Kr = o.pause_after > 0 ? std::min<int64_t>(K, o.pause_after - steps) : K;
+    Marker mk("solve steps");
     for (int64_t k = 0; k < Kr; ++k) {
       if ((s = run_fg<T>(ctx, st, V, pb.ldv, pb.nu, n, p, Lay.A_t, n, Lay.lam_t, r, R, d, alpha, Lay.f_t, Lay.glam_t,
                          Lay.G_t, n)) != SYMTD_OK)
@@ -402,6 +403,7 @@ symtd_status symtd_solve_state_bytes(const symtd_problem* pb, const symtd_solve_
 symtd_status symtd_solve(symtd_ctx* ctx, void* stream, const symtd_problem* pb, const symtd_solve_opts* o,
                          symtd_solve_result* out) {
   if (!ctx) return SYMTD_EINVAL;
+  Marker mk("symtd_solve");
   ctx->err.clear();
   symtd_status s = ctx->take_device_error();
   if (s != SYMTD_OK) return s;

@@ -325,6 +325,7 @@ symtd_status symtd_adam_opts_default(symtd_adam_opts* o) {
 symtd_status symtd_solve_adam(symtd_ctx* ctx, void* stream, const symtd_problem* pb, const symtd_adam_opts* o,
                               symtd_solve_result* out) {
   if (!ctx) return SYMTD_EINVAL;
+  Marker mk("symtd_solve_adam");
   ctx->err.clear();
   symtd_status rc = ctx->take_device_error();
   if (rc != SYMTD_OK) return rc;

@@ -17,7 +17,9 @@ import ctypes
 import os
 
 PKG_DIR = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG_DIR, "libsymtd.so")
+# SYMTD_LIBRARY names another build of the same library (the host-sanitizer
+# build of the CPU tests); by default the in-tree libsymtd.so
+LIB_PATH = os.environ.get("SYMTD_LIBRARY") or os.path.join(PKG_DIR, "libsymtd.so")
 
 SYMTD_OK = 0
 NOALLOC_SCRATCH_BYTES = 64 << 20   # SYMTD_NOALLOC_SCRATCH_BYTES of include/symtd.h

@@ -71,10 +71,10 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
                    "paper_1911_03813_amd/csrc/kcommon.hpp", "paper_1911_03813_amd/csrc/lp_kernels.hip",
                    "paper_1911_03813_amd/csrc/lp.hpp")
-TRAFFIC_SHA = "bffff4d4e31a05f9"
-TRAFFIC_BYTES = {("fp32", "gemm1"): 506.5e6, ("fp32", "gemm2"): 475.4e6,
-                 ("fp64", "gemm1"): 1088.5e6, ("fp64", "gemm2"): 948.5e6,
-                 ("fp16", "gemm1"): 273.5e6, ("fp16", "gemm2"): 242.3e6,
+TRAFFIC_SHA = "985ca03782c8e81d"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 506.9e6, ("fp32", "gemm2"): 475.4e6,
+                 ("fp64", "gemm1"): 1084.7e6, ("fp64", "gemm2"): 948.5e6,
+                 ("fp16", "gemm1"): 273.4e6, ("fp16", "gemm2"): 242.3e6,
                  ("bf16x3", "gemm1"): 509.0e6, ("bf16x3", "gemm2"): 469.7e6}
 
 

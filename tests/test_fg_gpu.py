@@ -86,7 +86,7 @@ def test_unaligned_leading_dimension(ctx, kind):
     check(ctx, 64, 700, 20, 4, (5,), kind, ldv_pad=3)
 
 
-@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 8])
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 8, 11, 16])   # 16: the largest order the library takes
 def test_orders(ctx, d):
     check(ctx, 48, 2500, 12, d, (6, d), "f64")
     check(ctx, 48, 2500, 12, d, (6, d), "f32")

@@ -32,7 +32,7 @@ def gpu_alpha(ctx, V, nu, d, kind):
 
 
 @pytest.mark.parametrize("n,p,d", [(1, 1, 3), (10, 750, 3), (7, 129, 2), (33, 300, 4), (100, 5000, 4),
-                                   (257, 1000, 5), (1000, 4000, 3)])
+                                   (257, 1000, 5), (1000, 4000, 3), (40, 600, 11), (40, 600, 16)])
 @pytest.mark.parametrize("kind", ["f64", "f32"])
 def test_normx_parity(ctx, n, p, d, kind):
     print(f"case n={n} p={p} d={d} kind={kind}", flush=True)

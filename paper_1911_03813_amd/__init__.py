@@ -405,13 +405,18 @@ class _SolveCall:
         o.sigma = float(sigma)
         o.pause_after = int(pause_after)
         self.state_out = None
-        if pause_after > 0:
+        if pause_after > 0 or state is not None:
             nbytes = ctypes.c_size_t()
             _check(None, lib().symtd_solve_state_bytes(ctypes.byref(self.pb), ctypes.byref(o), int(trace_len),
                                                        ctypes.byref(nbytes)))
+        if pause_after > 0:
             self.state_out = ctypes.create_string_buffer(nbytes.value)
             o.state_out = ctypes.cast(self.state_out, ctypes.c_void_p)
         if state is not None:
+            # the library reads a whole state of this problem's size: refuse a shorter block here
+            if len(state) != nbytes.value:
+                raise SymtdError(-1, f"the saved state has {len(state)} bytes; a state of this problem and "
+                                     f"these options has {nbytes.value}")
             self.state_in = ctypes.create_string_buffer(bytes(state), len(state))
             o.state_in = ctypes.cast(self.state_in, ctypes.c_void_p)
         self.opts = o

@@ -96,6 +96,10 @@ def test_resume_refuses_another_problem_or_options(ctx):
         with pytest.raises(S.SymtdError) as e:
             S.symtd_solve(ctx, Vd, nud, d, r, state=state, **kw)
         assert e.value.status == -1
+    # a truncated state (the binding checks the length before the library reads it)
+    with pytest.raises(S.SymtdError) as e:
+        S.symtd_solve(ctx, Vd, nud, 3, 4, state=state[:-8], **kw)
+    assert e.value.status == -1 and "bytes" in str(e.value)
     # a corrupted header
     broken = bytearray(state)
     broken[0] ^= 0xFF

@@ -82,7 +82,7 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-template <typename T, int NT, bool DMA>
+template <typename T, int NT, bool DMA, bool NARROW>
 __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int NW = g1_waves<T>();
@@ -101,6 +101,12 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   constexpr int PART = NW * MT * NT * 4 * 64;    // elements of one block's published partial
   static_assert(NS == 2 || NS == 3, "the chunk loop below is written for two or three stages");
   static_assert(QPC >= 4 && (QPC & (QPC - 1)) == 0, "chunk run length");
+  static_assert(!NARROW || sizeof(T) == 8, "the narrow last column subtile is the fp64 one");
+  // NARROW: the launch's last column subtile holds at most 4 factor columns
+  // (the rest is zero padding) and is multiplied on the 4x4x4 form
+  // (NarrowMfma), a quarter of the matrix work of a 16x16x4 subtile; its
+  // accumulator is element 0 of acc[m][NT - 1] (the other three stay zero)
+  constexpr int NF = NARROW ? NT - 1 : NT;       // column subtiles on the 16x16x4 form
   // LDS stages as distinct objects, so that the compiler can tell the loads
   // filling one stage from the reads of another; each is padded to whole
   // rounds of pieces so that every thread moves the same number of them
@@ -217,15 +223,19 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 #pragma unroll
       for (int m = 0; m < MT; ++m) fv[b][m] = lv[swz(16 * (MT * wave + m) + c, q)];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) fa[b][t] = la[swz(16 * t + c, q)];
+      for (int t = 0; t < NF; ++t) fa[b][t] = la[swz(16 * t + c, q)];
+      if constexpr (NARROW) fa[b][NT - 1] = la[swz(16 * (NT - 1) + (c & 3), q)];
     };
     auto mfma = [&](int b) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+        for (int m = 0; m < MT; ++m) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(fv[b][m].e[s], fa[b][t].e[s], acc[m][t]);
+          for (int t = 0; t < NF; ++t) acc[m][t] = Mfma<T>::mac(fv[b][m].e[s], fa[b][t].e[s], acc[m][t]);
+          if constexpr (NARROW)
+            acc[m][NT - 1][0] = NarrowMfma::mac(fv[b][m].e[s], fa[b][NT - 1].e[s], acc[m][NT - 1][0]);
+        }
     };
     frag(0, 0);
 #pragma unroll
@@ -247,13 +257,17 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 #pragma unroll
       for (int m = 0; m < MT; ++m) fv[m] = lv[swz(16 * (MT * wave + m) + c, q)];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) fa[t] = la[swz(16 * t + c, q)];
+      for (int t = 0; t < NF; ++t) fa[t] = la[swz(16 * t + c, q)];
+      if constexpr (NARROW) fa[NT - 1] = la[swz(16 * (NT - 1) + (c & 3), q)];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+        for (int m = 0; m < MT; ++m) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(fv[m].e[s], fa[t].e[s], acc[m][t]);
+          for (int t = 0; t < NF; ++t) acc[m][t] = Mfma<T>::mac(fv[m].e[s], fa[t].e[s], acc[m][t]);
+          if constexpr (NARROW)
+            acc[m][NT - 1][0] = NarrowMfma::mac(fv[m].e[s], fa[NT - 1].e[s], acc[m][NT - 1][0]);
+        }
     }
   };
   // chunk kc of a slab, through the shortened product when it is the ragged last one
@@ -403,7 +417,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) nl[v] = 16 * b + Mfma<T>::row(g, v) < a.p ? (T)nlr[m][v] : T(0);
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
+          for (int t = 0; t < NF; ++t) {
             Quad<T> wq;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -412,6 +426,25 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
               wsum[t] += (double)wv * (double)acc[m][t][v];
             }
             if (b < a.nblk) vstore4(a.Wp + (((b * a.nt_tot + tg + t) * 64) + lane) * 4, wq);
+          }
+          if constexpr (NARROW) {
+            // lane (g, c) holds z at observation 16 b + 4 (c / 4) + g, which is
+            // row(g, v) with v = c / 4, and column c mod 4 of the subtile: its
+            // w goes to element v of packed quad (g, c mod 4); the quads of
+            // the padding columns (c >= 4) are written as zeros
+            const int v = c >> 2;
+            const T nv = v == 0 ? nl[0] : v == 1 ? nl[1] : v == 2 ? nl[2] : nl[3];
+            const T wv = nv * zp[m][NT - 1][0];
+            wsum[NT - 1] += (double)wv * (double)acc[m][NT - 1][0];
+            if (b < a.nblk) {
+              T* wb = a.Wp + ((b * a.nt_tot + tg + NT - 1) * 64 + 16 * g) * 4;
+              gstore(wb + (c & 3) * 4 + v, wv);
+              if (c >= 4) {
+                Quad<T> zq;
+                zero4(zq);
+                vstore4(wb + c * 4, zq);
+              }
+            }
           }
         }
       }
@@ -429,9 +462,15 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     double s = wsum[t];
+    const bool nar = NARROW && t == NT - 1;
+    if (nar) {
+      // the narrow subtile's column is c mod 4: first across the lanes c, c ^ 4, c ^ 8, c ^ 12
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 8);
+    }
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
-    if (g == 0) a.wpart[(blk * NW + wave) * (int64_t)a.rp + a.col0 + 16 * t + c] = s;
+    if (g == 0) a.wpart[(blk * NW + wave) * (int64_t)a.rp + a.col0 + 16 * t + c] = nar && c >= 4 ? 0.0 : s;
   }
   handoff_done(a.ho.epoch, B, epoch);
 }
@@ -770,9 +809,16 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_final(FinalArgs<T> a) {
 template <typename T, int NS2>
 struct Dispatch {
   template <int NTV>
-  static void g1(bool dma, dim3 grid, hipStream_t st, const G1Args<T>& a) {
-    if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
-    else hipLaunchKernelGGL((k_gemm1<T, NTV, false>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
+  static void g1(bool dma, bool narrow, dim3 grid, hipStream_t st, const G1Args<T>& a) {
+    if constexpr (sizeof(T) == 8) {
+      if (narrow) {
+        if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
+        else hipLaunchKernelGGL((k_gemm1<T, NTV, false, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
+        return;
+      }
+    }
+    if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true, false>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm1<T, NTV, false, false>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
   }
   template <int NTV>
   static void g2(bool vec, dim3 grid, hipStream_t st, const G2Args<T>& a) {
@@ -784,27 +830,27 @@ struct Dispatch {
 using DF32 = Dispatch<float, G2_STAGES_F32>;
 using DF64 = Dispatch<double, G2_STAGES_F64>;
 
-void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<float>& a) {
+void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<float>& a, bool) {
   switch (nt) {
-    case 1: DF32::g1<1>(vec, grid, st, a); break;
-    case 2: DF32::g1<2>(vec, grid, st, a); break;
-    case 3: DF32::g1<3>(vec, grid, st, a); break;
-    case 4: DF32::g1<4>(vec, grid, st, a); break;
-    case 5: DF32::g1<5>(vec, grid, st, a); break;
-    case 6: DF32::g1<6>(vec, grid, st, a); break;
-    case 7: DF32::g1<7>(vec, grid, st, a); break;
+    case 1: DF32::g1<1>(vec, false, grid, st, a); break;
+    case 2: DF32::g1<2>(vec, false, grid, st, a); break;
+    case 3: DF32::g1<3>(vec, false, grid, st, a); break;
+    case 4: DF32::g1<4>(vec, false, grid, st, a); break;
+    case 5: DF32::g1<5>(vec, false, grid, st, a); break;
+    case 6: DF32::g1<6>(vec, false, grid, st, a); break;
+    case 7: DF32::g1<7>(vec, false, grid, st, a); break;
     default: break;
   }
 }
-void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<double>& a) {
+void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<double>& a, bool narrow) {
   switch (nt) {
-    case 1: DF64::g1<1>(vec, grid, st, a); break;
-    case 2: DF64::g1<2>(vec, grid, st, a); break;
-    case 3: DF64::g1<3>(vec, grid, st, a); break;
-    case 4: DF64::g1<4>(vec, grid, st, a); break;
-    case 5: DF64::g1<5>(vec, grid, st, a); break;
-    case 6: DF64::g1<6>(vec, grid, st, a); break;
-    case 7: DF64::g1<7>(vec, grid, st, a); break;
+    case 1: DF64::g1<1>(vec, narrow, grid, st, a); break;
+    case 2: DF64::g1<2>(vec, narrow, grid, st, a); break;
+    case 3: DF64::g1<3>(vec, narrow, grid, st, a); break;
+    case 4: DF64::g1<4>(vec, narrow, grid, st, a); break;
+    case 5: DF64::g1<5>(vec, narrow, grid, st, a); break;
+    case 6: DF64::g1<6>(vec, narrow, grid, st, a); break;
+    case 7: DF64::g1<7>(vec, narrow, grid, st, a); break;
     default: break;
   }
 }

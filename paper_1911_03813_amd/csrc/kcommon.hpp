@@ -38,6 +38,20 @@ template <> struct Mfma<double> {
   }
 };
 
+// v_mfma_f64_4x4x4f64: four 4x4x4 products at once.  With lane = 16 g + c
+// and c = 4 i + x (checked on gfx950 hardware), block i takes the first
+// operand of lane (g, c) as its row x, k slot g, and the second as its k slot
+// g, column x; lane 16 x + 4 i + j receives block i's D[x][j].  So when lane
+// (g, c) supplies row c of a 16-row subtile and column c mod 4 of a 4-column
+// operand, both at k slot g, the four blocks are the subtile's four groups of
+// four rows against the same 4 columns, and lane (g, c) receives the product
+// at row 4 (c / 4) + g, column c mod 4.
+struct NarrowMfma {
+  static __device__ __forceinline__ double mac(double a, double b, double c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
 // Four consecutive elements of a column held by one lane.
 template <typename T> struct Quad { T e[4]; };
 

@@ -478,9 +478,14 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 // ---------------------------------------------------------------------------
 // gemm2: partial Y = V W over one split of the observations
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int NS, bool VEC>
+template <typename T, int NT, int NS, bool VEC, bool NARROW>
 __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
   using acc_t = typename Mfma<T>::acc_t;
+  static_assert(!NARROW || sizeof(T) == 8, "the narrow last column subtile is the fp64 one");
+  // NARROW: the last column subtile holds at most 4 columns of W and runs on
+  // the 4x4x4 form (NarrowMfma) into accn[m]; lane (g, c) loads the W quad
+  // of column c mod 4
+  constexpr int NF = NARROW ? NT - 1 : NT;
   // Block -> (row block x, split y).  Consecutive block ids go to different
   // XCDs (id mod 8), so the row blocks of one split get ids with the same
   // residue mod 8: they run on one XCD and share the W slabs in its L2.
@@ -505,17 +510,29 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
   const int64_t b1 = min((int64_t)a.nblk, b0 + a.blk_per_split);
   const int tg = a.col0 >> 4;
 
-  acc_t acc[4][NT];
+  acc_t acc[4][NF > 0 ? NF : 1];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
+    for (int t = 0; t < NF; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
+  double accn[4] = {0.0, 0.0, 0.0, 0.0};
+  // the narrow accumulators stay in AGPRs beside the others (left to the
+  // compiler, they move to VGPRs and back every iteration)
+  auto pin_narrow = [&]() {
+    if constexpr (NARROW) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) asm("" : "+a"(accn[m]));
+    }
+  };
+  pin_narrow();
 
   Quad<T> vb[NS][4];
   Quad<T> wb[NS][NT];
   auto issue = [&](int buf, int64_t b) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) vload4(wb[buf][t], a.Wp + (((b * a.nt_tot + tg + t) * 64) + lane) * 4);
+    for (int t = 0; t < NF; ++t) vload4(wb[buf][t], a.Wp + (((b * a.nt_tot + tg + t) * 64) + lane) * 4);
+    if constexpr (NARROW)
+      vload4(wb[buf][NT - 1], a.Wp + (((b * a.nt_tot + tg + NT - 1) * 64) + 16 * g + (c & 3)) * 4);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       int64_t l = 16 * b + Mfma<T>::row(g, s);
@@ -533,9 +550,12 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(vb[buf][s].e[m], wb[buf][t].e[s], acc[m][t]);
+        for (int t = 0; t < NF; ++t) acc[m][t] = Mfma<T>::mac(vb[buf][s].e[m], wb[buf][t].e[s], acc[m][t]);
+        if constexpr (NARROW) accn[m] = NarrowMfma::mac(vb[buf][s].e[m], wb[buf][NT - 1].e[s], accn[m]);
+      }
+    pin_narrow();
   };
 
   const int64_t Q = b1 - b0;
@@ -564,7 +584,7 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
 
   // acc[m][t][v] = Y[ibase + 4 row(g, v) + m][col0 + 16t + c]
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
+  for (int t = 0; t < NF; ++t) {
     T* col = a.Ypart + ((int64_t)y * a.rp + a.col0 + 16 * t + c) * a.npad;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -573,6 +593,15 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
       for (int m = 0; m < 4; ++m) q.e[m] = acc[m][t][v];
       vstore4(col + ibase + 4 * Mfma<T>::row(g, v), q);
     }
+  }
+  if constexpr (NARROW) {
+    // accn[m] = Y[ibase + 4 (4 (c / 4) + g) + m][col0 + 16 (NT - 1) + c mod 4]; the
+    // padding columns of Y are not written (the closing step reads columns below r only)
+    T* col = a.Ypart + ((int64_t)y * a.rp + a.col0 + 16 * (NT - 1) + (c & 3)) * a.npad;
+    Quad<T> q;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) q.e[m] = (T)accn[m];
+    vstore4(col + ibase + 4 * (4 * (c >> 2) + g), q);
   }
 }
 
@@ -821,9 +850,16 @@ struct Dispatch {
     else hipLaunchKernelGGL((k_gemm1<T, NTV, false, false>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
   }
   template <int NTV>
-  static void g2(bool vec, dim3 grid, hipStream_t st, const G2Args<T>& a) {
-    if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, false>), grid, dim3(256), 0, st, a);
+  static void g2(bool vec, bool narrow, dim3 grid, hipStream_t st, const G2Args<T>& a) {
+    if constexpr (sizeof(T) == 8) {
+      if (narrow) {
+        if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, true, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, false, true>), grid, dim3(256), 0, st, a);
+        return;
+      }
+    }
+    if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, true, false>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, false, false>), grid, dim3(256), 0, st, a);
   }
 };
 
@@ -854,27 +890,27 @@ void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<doub
     default: break;
   }
 }
-void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a) {
+void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a, bool) {
   switch (nt) {
-    case 1: DF32::g2<1>(vec, grid, st, a); break;
-    case 2: DF32::g2<2>(vec, grid, st, a); break;
-    case 3: DF32::g2<3>(vec, grid, st, a); break;
-    case 4: DF32::g2<4>(vec, grid, st, a); break;
-    case 5: DF32::g2<5>(vec, grid, st, a); break;
-    case 6: DF32::g2<6>(vec, grid, st, a); break;
-    case 7: DF32::g2<7>(vec, grid, st, a); break;
+    case 1: DF32::g2<1>(vec, false, grid, st, a); break;
+    case 2: DF32::g2<2>(vec, false, grid, st, a); break;
+    case 3: DF32::g2<3>(vec, false, grid, st, a); break;
+    case 4: DF32::g2<4>(vec, false, grid, st, a); break;
+    case 5: DF32::g2<5>(vec, false, grid, st, a); break;
+    case 6: DF32::g2<6>(vec, false, grid, st, a); break;
+    case 7: DF32::g2<7>(vec, false, grid, st, a); break;
     default: break;
   }
 }
-void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<double>& a) {
+void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<double>& a, bool narrow) {
   switch (nt) {
-    case 1: DF64::g2<1>(vec, grid, st, a); break;
-    case 2: DF64::g2<2>(vec, grid, st, a); break;
-    case 3: DF64::g2<3>(vec, grid, st, a); break;
-    case 4: DF64::g2<4>(vec, grid, st, a); break;
-    case 5: DF64::g2<5>(vec, grid, st, a); break;
-    case 6: DF64::g2<6>(vec, grid, st, a); break;
-    case 7: DF64::g2<7>(vec, grid, st, a); break;
+    case 1: DF64::g2<1>(vec, narrow, grid, st, a); break;
+    case 2: DF64::g2<2>(vec, narrow, grid, st, a); break;
+    case 3: DF64::g2<3>(vec, narrow, grid, st, a); break;
+    case 4: DF64::g2<4>(vec, narrow, grid, st, a); break;
+    case 5: DF64::g2<5>(vec, narrow, grid, st, a); break;
+    case 6: DF64::g2<6>(vec, narrow, grid, st, a); break;
+    case 7: DF64::g2<7>(vec, narrow, grid, st, a); break;
     default: break;
   }
 }

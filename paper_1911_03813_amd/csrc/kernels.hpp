@@ -152,8 +152,8 @@ struct ReduceArgs {
 // (fp64 only: it is then multiplied on the 4x4x4 form; ignored for fp32)
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<float>& a, bool narrow = false);
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<double>& a, bool narrow = false);
-void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a);
-void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<double>& a);
+void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a, bool narrow = false);
+void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<double>& a, bool narrow = false);
 void launch_prep(int64_t blocks, hipStream_t st, const PrepArgs<float>& a);
 void launch_prep(int64_t blocks, hipStream_t st, const PrepArgs<double>& a);
 void launch_final(hipStream_t st, const FinalArgs<float>& a);

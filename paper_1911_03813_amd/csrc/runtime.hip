@@ -262,8 +262,9 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
     G2Args<T> a2{V, ldv, (int)n, (int)p, Wp, P.nt_tot, P.rp, 16 * t0, P.nblk, P.blk_per_split,
                  P.nsplit, P.rowblocks, Ypart, P.npad};
     const unsigned blocks = (unsigned)(P.rowblocks * 8 * ((P.nsplit + 7) / 8));
+    const bool narrow = f64 && r - (16 * (int64_t)t0 + 16 * (nt - 1)) <= 4;
     ctx->prof_begin(1, st);
-    launch_gemm2(nt, vecV && (n % 4) == 0, dim3(blocks), st, a2);
+    launch_gemm2(nt, vecV && (n % 4) == 0, dim3(blocks), st, a2, narrow);
     ctx->prof_end(1, st);
   }
   // G_A, w, u, g_lambda, f

@@ -92,6 +92,15 @@ def test_orders(ctx, d):
     check(ctx, 48, 2500, 12, d, (6, d), "f32")
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 18, 35, 52, 100, 116, 5, 21])
+def test_narrow_last_subtile(ctx, r):
+    # fp64: a last column subtile with r mod 16 in 1..4 factor columns runs on
+    # the 4x4x4 form in both products (r = 116: the second column group is that
+    # subtile alone); r = 5 and 21 take the 16x16x4 form throughout
+    check(ctx, 70, 3000, r, 3, (12, r), "f64")
+    check(ctx, 33, 1001, r, 4, (13, r), "f64")
+
+
 def test_exact_solution(ctx):
     # r = p, A = V, lambda = nu: f = 0 and the gradient vanishes
     n, p, d = 12, 40, 3

@@ -101,11 +101,11 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   constexpr int PART = NW * MT * NT * 4 * 64;    // elements of one block's published partial
   static_assert(NS == 2 || NS == 3, "the chunk loop below is written for two or three stages");
   static_assert(QPC >= 4 && (QPC & (QPC - 1)) == 0, "chunk run length");
-  static_assert(!NARROW || sizeof(T) == 8, "the narrow last column subtile is the fp64 one");
   // NARROW: the launch's last column subtile holds at most 4 factor columns
-  // (the rest is zero padding) and is multiplied on the 4x4x4 form
-  // (NarrowMfma), a quarter of the matrix work of a 16x16x4 subtile; its
-  // accumulator is element 0 of acc[m][NT - 1] (the other three stay zero)
+  // (the rest is zero padding) and is multiplied on the narrow form
+  // (Narrow<T>), a quarter of the matrix work of a 16x16x4 subtile; its
+  // accumulator is acc[m][NT - 1]: element 0 in fp64 (the other three stay
+  // zero), all four in fp32 (one lane group's share, see Narrow<float>)
   constexpr int NF = NARROW ? NT - 1 : NT;       // column subtiles on the 16x16x4 form
   // LDS stages as distinct objects, so that the compiler can tell the loads
   // filling one stage from the reads of another; each is padded to whole
@@ -233,8 +233,12 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
         for (int m = 0; m < MT; ++m) {
 #pragma unroll
           for (int t = 0; t < NF; ++t) acc[m][t] = Mfma<T>::mac(fv[b][m].e[s], fa[b][t].e[s], acc[m][t]);
-          if constexpr (NARROW)
-            acc[m][NT - 1][0] = NarrowMfma::mac(fv[b][m].e[s], fa[b][NT - 1].e[s], acc[m][NT - 1][0]);
+          if constexpr (NARROW) {
+            if constexpr (sizeof(T) == 8)
+              acc[m][NT - 1][0] = Narrow<T>::mac(fv[b][m].e[s], fa[b][NT - 1].e[s], acc[m][NT - 1][0]);
+            else
+              acc[m][NT - 1] = Narrow<T>::mac(fv[b][m].e[s], fa[b][NT - 1].e[s], acc[m][NT - 1]);
+          }
         }
     };
     frag(0, 0);
@@ -265,8 +269,12 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
         for (int m = 0; m < MT; ++m) {
 #pragma unroll
           for (int t = 0; t < NF; ++t) acc[m][t] = Mfma<T>::mac(fv[m].e[s], fa[t].e[s], acc[m][t]);
-          if constexpr (NARROW)
-            acc[m][NT - 1][0] = NarrowMfma::mac(fv[m].e[s], fa[NT - 1].e[s], acc[m][NT - 1][0]);
+          if constexpr (NARROW) {
+            if constexpr (sizeof(T) == 8)
+              acc[m][NT - 1][0] = Narrow<T>::mac(fv[m].e[s], fa[NT - 1].e[s], acc[m][NT - 1][0]);
+            else
+              acc[m][NT - 1] = Narrow<T>::mac(fv[m].e[s], fa[NT - 1].e[s], acc[m][NT - 1]);
+          }
         }
     }
   };
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
             }
             if (b < a.nblk) vstore4(a.Wp + (((b * a.nt_tot + tg + t) * 64) + lane) * 4, wq);
           }
-          if constexpr (NARROW) {
+          if constexpr (NARROW && sizeof(T) == 8) {
             // lane (g, c) holds z at observation 16 b + 4 (c / 4) + g, which is
             // row(g, v) with v = c / 4, and column c mod 4 of the subtile: its
             // w goes to element v of packed quad (g, c mod 4); the quads of
@@ -444,6 +452,37 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
                 zero4(zq);
                 vstore4(wb + c * 4, zq);
               }
+            }
+          } else if constexpr (NARROW) {
+            // the four lane groups' shares add up to z at observations
+            // 16 b + 4 (c / 4) + x (element x), column c mod 4; with the fp32
+            // row(g, v) = 4 g + v these rows are packed quad (c / 4, c mod 4),
+            // which the lanes of group 0 write (their weights loaded here);
+            // the quads of the padding columns (c >= 4) are written as zeros
+            acc_t z = acc[m][NT - 1];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              z[x] += __shfl_xor(z[x], 16);
+              z[x] += __shfl_xor(z[x], 32);
+            }
+            T* wb = a.Wp + (b * a.nt_tot + tg + NT - 1) * 64 * 4;
+            if (g == 0) {
+              Quad<T> wq;
+#pragma unroll
+              for (int x = 0; x < 4; ++x) {
+                const int64_t l = 16 * b + 4 * (c >> 2) + x;
+                const T nv = l < a.p ? (T)a.nu[l] : T(0);
+                T zp1 = T(1);
+                for (int e = 0; e < dm1; ++e) zp1 *= z[x];
+                wq.e[x] = nv * zp1;
+                wsum[NT - 1] += (double)wq.e[x] * (double)z[x];
+              }
+              if (b < a.nblk) vstore4(wb + (16 * (c >> 2) + (c & 3)) * 4, wq);
+            }
+            if (c >= 4 && b < a.nblk) {
+              Quad<T> zq;
+              zero4(zq);
+              vstore4(wb + (16 * g + c) * 4, zq);
             }
           }
         }
@@ -481,9 +520,8 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 template <typename T, int NT, int NS, bool VEC, bool NARROW>
 __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
   using acc_t = typename Mfma<T>::acc_t;
-  static_assert(!NARROW || sizeof(T) == 8, "the narrow last column subtile is the fp64 one");
   // NARROW: the last column subtile holds at most 4 columns of W and runs on
-  // the 4x4x4 form (NarrowMfma) into accn[m]; lane (g, c) loads the W quad
+  // the narrow form (Narrow<T>) into accn[m]; lane (g, c) loads the W quad
   // of column c mod 4
   constexpr int NF = NARROW ? NT - 1 : NT;
   // Block -> (row block x, split y).  Consecutive block ids go to different
@@ -515,7 +553,10 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int t = 0; t < NF; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
-  double accn[4] = {0.0, 0.0, 0.0, 0.0};
+  using nacc_t = typename Narrow<T>::acc_t;
+  nacc_t accn[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) accn[m] = nacc_t{0};
   // the narrow accumulators stay in AGPRs beside the others (left to the
   // compiler, they move to VGPRs and back every iteration)
   auto pin_narrow = [&]() {
@@ -553,7 +594,7 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
       for (int m = 0; m < 4; ++m) {
 #pragma unroll
         for (int t = 0; t < NF; ++t) acc[m][t] = Mfma<T>::mac(vb[buf][s].e[m], wb[buf][t].e[s], acc[m][t]);
-        if constexpr (NARROW) accn[m] = NarrowMfma::mac(vb[buf][s].e[m], wb[buf][NT - 1].e[s], accn[m]);
+        if constexpr (NARROW) accn[m] = Narrow<T>::mac(vb[buf][s].e[m], wb[buf][NT - 1].e[s], accn[m]);
       }
     pin_narrow();
   };
@@ -594,14 +635,35 @@ __global__ __launch_bounds__(256) void k_gemm2(G2Args<T> a) {
       vstore4(col + ibase + 4 * Mfma<T>::row(g, v), q);
     }
   }
-  if constexpr (NARROW) {
-    // accn[m] = Y[ibase + 4 (4 (c / 4) + g) + m][col0 + 16 (NT - 1) + c mod 4]; the
-    // padding columns of Y are not written (the closing step reads columns below r only)
+  // the narrow subtile: the padding columns of Y are not written (the
+  // closing step reads columns below r only)
+  if constexpr (NARROW && sizeof(T) == 8) {
+    // accn[m] = Y[ibase + 4 (4 (c / 4) + g) + m][col0 + 16 (NT - 1) + c mod 4]
     T* col = a.Ypart + ((int64_t)y * a.rp + a.col0 + 16 * (NT - 1) + (c & 3)) * a.npad;
     Quad<T> q;
 #pragma unroll
     for (int m = 0; m < 4; ++m) q.e[m] = (T)accn[m];
     vstore4(col + ibase + 4 * (4 * (c >> 2) + g), q);
+  } else if constexpr (NARROW) {
+    // summed over the four lane groups, accn[m][x] = Y[ibase + 4 (4 (c / 4) + x) + m]
+    // [col0 + 16 (NT - 1) + c mod 4]; the lanes of group 0 write them
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        accn[m][x] += __shfl_xor(accn[m][x], 16);
+        accn[m][x] += __shfl_xor(accn[m][x], 32);
+      }
+    if (g == 0) {
+      T* col = a.Ypart + ((int64_t)y * a.rp + a.col0 + 16 * (NT - 1) + (c & 3)) * a.npad;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        Quad<T> q;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) q.e[m] = accn[m][x];
+        vstore4(col + ibase + 4 * (4 * (c >> 2) + x), q);
+      }
+    }
   }
 }
 
@@ -839,24 +901,20 @@ template <typename T, int NS2>
 struct Dispatch {
   template <int NTV>
   static void g1(bool dma, bool narrow, dim3 grid, hipStream_t st, const G1Args<T>& a) {
-    if constexpr (sizeof(T) == 8) {
-      if (narrow) {
-        if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
-        else hipLaunchKernelGGL((k_gemm1<T, NTV, false, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
-        return;
-      }
+    if (narrow) {
+      if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
+      else hipLaunchKernelGGL((k_gemm1<T, NTV, false, true>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
+      return;
     }
     if (dma) hipLaunchKernelGGL((k_gemm1<T, NTV, true, false>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
     else hipLaunchKernelGGL((k_gemm1<T, NTV, false, false>), grid, dim3(64 * g1_waves<T>()), 0, st, a);
   }
   template <int NTV>
   static void g2(bool vec, bool narrow, dim3 grid, hipStream_t st, const G2Args<T>& a) {
-    if constexpr (sizeof(T) == 8) {
-      if (narrow) {
-        if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, true, true>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, false, true>), grid, dim3(256), 0, st, a);
-        return;
-      }
+    if (narrow) {
+      if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, true, true>), grid, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, false, true>), grid, dim3(256), 0, st, a);
+      return;
     }
     if (vec) hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, true, false>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_gemm2<T, NTV, NS2, false, false>), grid, dim3(256), 0, st, a);
@@ -866,15 +924,15 @@ struct Dispatch {
 using DF32 = Dispatch<float, G2_STAGES_F32>;
 using DF64 = Dispatch<double, G2_STAGES_F64>;
 
-void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<float>& a, bool) {
+void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<float>& a, bool narrow) {
   switch (nt) {
-    case 1: DF32::g1<1>(vec, false, grid, st, a); break;
-    case 2: DF32::g1<2>(vec, false, grid, st, a); break;
-    case 3: DF32::g1<3>(vec, false, grid, st, a); break;
-    case 4: DF32::g1<4>(vec, false, grid, st, a); break;
-    case 5: DF32::g1<5>(vec, false, grid, st, a); break;
-    case 6: DF32::g1<6>(vec, false, grid, st, a); break;
-    case 7: DF32::g1<7>(vec, false, grid, st, a); break;
+    case 1: DF32::g1<1>(vec, narrow, grid, st, a); break;
+    case 2: DF32::g1<2>(vec, narrow, grid, st, a); break;
+    case 3: DF32::g1<3>(vec, narrow, grid, st, a); break;
+    case 4: DF32::g1<4>(vec, narrow, grid, st, a); break;
+    case 5: DF32::g1<5>(vec, narrow, grid, st, a); break;
+    case 6: DF32::g1<6>(vec, narrow, grid, st, a); break;
+    case 7: DF32::g1<7>(vec, narrow, grid, st, a); break;
     default: break;
   }
 }
@@ -890,15 +948,15 @@ void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<doub
     default: break;
   }
 }
-void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a, bool) {
+void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a, bool narrow) {
   switch (nt) {
-    case 1: DF32::g2<1>(vec, false, grid, st, a); break;
-    case 2: DF32::g2<2>(vec, false, grid, st, a); break;
-    case 3: DF32::g2<3>(vec, false, grid, st, a); break;
-    case 4: DF32::g2<4>(vec, false, grid, st, a); break;
-    case 5: DF32::g2<5>(vec, false, grid, st, a); break;
-    case 6: DF32::g2<6>(vec, false, grid, st, a); break;
-    case 7: DF32::g2<7>(vec, false, grid, st, a); break;
+    case 1: DF32::g2<1>(vec, narrow, grid, st, a); break;
+    case 2: DF32::g2<2>(vec, narrow, grid, st, a); break;
+    case 3: DF32::g2<3>(vec, narrow, grid, st, a); break;
+    case 4: DF32::g2<4>(vec, narrow, grid, st, a); break;
+    case 5: DF32::g2<5>(vec, narrow, grid, st, a); break;
+    case 6: DF32::g2<6>(vec, narrow, grid, st, a); break;
+    case 7: DF32::g2<7>(vec, narrow, grid, st, a); break;
     default: break;
   }
 }

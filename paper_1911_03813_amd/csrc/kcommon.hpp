@@ -38,17 +38,33 @@ template <> struct Mfma<double> {
   }
 };
 
-// v_mfma_f64_4x4x4f64: four 4x4x4 products at once.  With lane = 16 g + c
-// and c = 4 i + x (checked on gfx950 hardware), block i takes the first
-// operand of lane (g, c) as its row x, k slot g, and the second as its k slot
-// g, column x; lane 16 x + 4 i + j receives block i's D[x][j].  So when lane
-// (g, c) supplies row c of a 16-row subtile and column c mod 4 of a 4-column
-// operand, both at k slot g, the four blocks are the subtile's four groups of
-// four rows against the same 4 columns, and lane (g, c) receives the product
-// at row 4 (c / 4) + g, column c mod 4.
-struct NarrowMfma {
+// The narrow forms, for a column subtile of at most 4 columns (lane =
+// 16 g + c; layouts checked on gfx950 hardware).  In both, lane (g, c)
+// supplies row c of a 16-row subtile as the first operand and column c mod 4
+// of a 4-column operand as the second, at the k value of its lane group g.
+//
+// fp64, v_mfma_f64_4x4x4f64 (four 4x4x4 products): with c = 4 i + x, block i
+// takes lane (g, c)'s first operand as row x at k slot g and its second as k
+// slot g of column x, and lane 16 x + 4 i + j receives block i's D[x][j]:
+// lane (g, c) receives the full product at row 4 (c / 4) + g, column c mod 4.
+//
+// fp32, v_mfma_f32_4x4x1f32 (sixteen 4x4x1 products, K = 1): block 4 g + c / 4
+// is the four lanes 4 (c / 4) + x of group g; it takes lane x's first operand
+// as row x and lane j's second as column j, and lane j of the block receives
+// D[x][j] in element x.  So lane (g, c) receives rows 4 (c / 4) + x (element
+// x), column c mod 4, summed over the k values of its own lane group only:
+// the four groups' accumulators add up to the product.
+template <typename T> struct Narrow;
+template <> struct Narrow<double> {
+  using acc_t = double;
   static __device__ __forceinline__ double mac(double a, double b, double c) {
     return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Narrow<float> {
+  using acc_t = v4f;
+  static __device__ __forceinline__ v4f mac(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
   }
 };
 

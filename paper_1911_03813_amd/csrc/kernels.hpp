@@ -149,7 +149,7 @@ struct ReduceArgs {
 };
 
 // narrow: the launch's last column subtile holds at most 4 factor columns
-// (fp64 only: it is then multiplied on the 4x4x4 form; ignored for fp32)
+// (it is then multiplied on the narrow MFMA form, Narrow<T>)
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<float>& a, bool narrow = false);
 void launch_gemm1(int nt, bool vec, dim3 grid, hipStream_t st, const G1Args<double>& a, bool narrow = false);
 void launch_gemm2(int nt, bool vec, dim3 grid, hipStream_t st, const G2Args<float>& a, bool narrow = false);

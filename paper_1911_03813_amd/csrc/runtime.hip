@@ -250,8 +250,8 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
     const int nt = std::min(P.nt1, P.nt_tot - t0);
     G1Args<T> a1{V, ldv, nu, (int)n, (int)p, A, lda, (int)r, 16 * t0, P.nt_tot, P.rp, P.nblk,
                  P.nslab, P.nblocks, d, Apad, P.ldap, Wp, wpart, part, ctx->handoff()};
-    // the launch's last column subtile: at most 4 factor columns go on the 4x4x4 form (fp64)
-    const bool narrow = f64 && r - (16 * (int64_t)t0 + 16 * (nt - 1)) <= 4;
+    // the launch's last column subtile: at most 4 factor columns go on the narrow form
+    const bool narrow = r - (16 * (int64_t)t0 + 16 * (nt - 1)) <= 4;
     ctx->prof_begin(0, st);
     launch_gemm1(nt, dma, dim3(P.nblocks), st, a1, narrow);
     ctx->prof_end(0, st);
@@ -262,7 +262,7 @@ symtd_status run_fg(symtd_ctx* ctx, hipStream_t st, const T* V, int64_t ldv, con
     G2Args<T> a2{V, ldv, (int)n, (int)p, Wp, P.nt_tot, P.rp, 16 * t0, P.nblk, P.blk_per_split,
                  P.nsplit, P.rowblocks, Ypart, P.npad};
     const unsigned blocks = (unsigned)(P.rowblocks * 8 * ((P.nsplit + 7) / 8));
-    const bool narrow = f64 && r - (16 * (int64_t)t0 + 16 * (nt - 1)) <= 4;
+    const bool narrow = r - (16 * (int64_t)t0 + 16 * (nt - 1)) <= 4;
     ctx->prof_begin(1, st);
     launch_gemm2(nt, vecV && (n % 4) == 0, dim3(blocks), st, a2, narrow);
     ctx->prof_end(1, st);

@@ -65,12 +65,22 @@ def test_fg_multi_matches_oracle(ctx, kind, n, p, r, models):
         cols = slice(k * r, (k + 1) * r)
         ef, eg, eG = compare_fg((f[k], g[cols], G[:, cols]), V, nu, As[k], lams[k], d, alpha, kind)
         assert ef <= TOL[kind] and eg <= TOL[kind] and eG <= TOL[kind], (k, ef, eg, eG)
-        # and exactly what the single-model call gives for that model
+        # and exactly what the single-model call gives for that model, when
+        # both calls multiply their last column subtile in the same form (a
+        # last subtile of 1..4 columns takes the narrow MFMA form, whose fp32
+        # sums run in another order); otherwise the single call is checked
+        # against the oracle in its own right
         f1, g1, G1 = S.symtd_fg(ctx, Vd, nud, to_dev(As[k], dt), to_dev(lams[k], torch.float64), d, alpha)
         torch.cuda.synchronize()
-        assert f1.cpu().numpy()[0] == f[k]
-        assert np.array_equal(g1.cpu().numpy(), g[cols])
-        assert np.array_equal(G1.cpu().numpy().astype(np.float64), G[:, cols])
+        f1, g1, G1 = f1.cpu().numpy()[0], g1.cpu().numpy(), G1.cpu().numpy().astype(np.float64)
+        narrow = lambda cols_total: 1 <= cols_total % 16 <= 4
+        if narrow(r) == narrow(r * models):
+            assert f1 == f[k]
+            assert np.array_equal(g1, g[cols])
+            assert np.array_equal(G1, G[:, cols])
+        else:
+            e1 = compare_fg((f1, g1, G1), V, nu, As[k], lams[k], d, alpha, kind)
+            assert max(e1) <= TOL[kind], e1
 
 
 # --- starts --------------------------------------------------------------------------

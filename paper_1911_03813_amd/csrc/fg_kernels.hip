@@ -37,7 +37,7 @@ namespace symtd {
 // 16*MT*NW observations (16*MT per wave, MT = g1_mt<T>()).  The k range (the n covariates) is cut into
 // chunks of KCH = 4*QPC; for every chunk the block moves the slab's
 // observation columns and the factor columns into LDS, each column as one
-// contiguous run of G1_RUN bytes (QPC quads of 4 elements), and the waves read
+// contiguous run of g1_run<T>() bytes (QPC quads of 4 elements), and the waves read
 // their MFMA fragments from LDS.  LDS holds a column's quads at a swizzled
 // slot (quad q of column col at col*QPC + (q ^ (col mod QPC))), so the 16
 // columns of one fragment read fall in distinct banks.
@@ -46,7 +46,7 @@ namespace symtd {
 // chunk's 16-byte pieces go from global memory straight into LDS
 // (global_load_lds): every lane fetches the piece whose LDS slot is its own,
 // and every thread issues the same number of pieces per chunk, so a wave can
-// wait for exactly one chunk with vmcnt.  Chunks rotate through G1_STAGES
+// wait for exactly one chunk with vmcnt.  Chunks rotate through g1_stages<T>()
 // LDS stages: with two, the next chunk is in flight while one is multiplied
 // (with three, the next two).  Other
 // layouts pass through registers with two stages.  The factors are read from
@@ -70,7 +70,7 @@ namespace symtd {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct G1Shape {
-  static constexpr int QPC = G1_RUN / (4 * (int)sizeof(T));   // quads per column per chunk
+  static constexpr int QPC = g1_run<T>() / (4 * (int)sizeof(T));   // quads per column per chunk
   static constexpr int KCH = 4 * QPC;                         // k values per chunk
 };
 
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   constexpr int NW = g1_waves<T>();
   constexpr int MT = g1_mt<T>();
   constexpr int NTH = 64 * NW;
-  constexpr int NS = G1_STAGES;
+  constexpr int NS = g1_stages<T>();
   constexpr int QPC = G1Shape<T>::QPC;
   constexpr int KCH = G1Shape<T>::KCH;
   constexpr int H = (int)sizeof(T) / 4;          // 16-byte pieces per quad

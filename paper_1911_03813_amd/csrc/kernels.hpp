@@ -15,31 +15,40 @@ constexpr int NT_MAX_G1_F32 = 7;
 constexpr int NT_MAX_G1_F64 = 7;
 constexpr int NT_MAX_G2_F32 = 7;
 constexpr int NT_MAX_G2_F64 = 7;
-// gemm1 shape: waves per block, M subtiles (16 observations) per wave, bytes
-// of one column run per chunk, and LDS stages of the chunk ring.
+// gemm1 shape of the fp32 kernel: waves per block, M subtiles (16
+// observations) per wave, bytes of one column run per chunk, and LDS stages
+// of the chunk ring; and the chunk run and stages of the fp64 kernel.
+// fp32: eight one-subtile waves (two per SIMD) on 128-byte chunks in three
+// stages (96 KiB of LDS); fp64: 256-byte chunks in two stages (128 KiB).
 #ifndef SYMTD_G1_WAVES
-#define SYMTD_G1_WAVES 4
+#define SYMTD_G1_WAVES 8
 #endif
 #ifndef SYMTD_G1_MT
-#define SYMTD_G1_MT 2
+#define SYMTD_G1_MT 1
 #endif
 #ifndef SYMTD_G1_RUN
-#define SYMTD_G1_RUN 256
+#define SYMTD_G1_RUN 128
 #endif
 #ifndef SYMTD_G1_STAGES
-#define SYMTD_G1_STAGES 2
+#define SYMTD_G1_STAGES 3
+#endif
+#ifndef SYMTD_G1_RUN_F64
+#define SYMTD_G1_RUN_F64 256
+#endif
+#ifndef SYMTD_G1_STAGES_F64
+#define SYMTD_G1_STAGES_F64 2
 #endif
 constexpr int G1_WAVES = SYMTD_G1_WAVES;
 constexpr int G1_MT = SYMTD_G1_MT;
-constexpr int G1_RUN = SYMTD_G1_RUN;
-constexpr int G1_STAGES = SYMTD_G1_STAGES;
+template <typename T> constexpr int g1_run() { return sizeof(T) == 8 ? SYMTD_G1_RUN_F64 : SYMTD_G1_RUN; }
+template <typename T> constexpr int g1_stages() { return sizeof(T) == 8 ? SYMTD_G1_STAGES_F64 : SYMTD_G1_STAGES; }
 // M subtiles per wave of the first product: fp64 takes one, so that seven
 // column subtiles of fp64 accumulators fit the register file and r <= 112
 // needs one launch (V read once)
 template <typename T> constexpr int g1_mt() { return sizeof(T) == 8 ? 1 : G1_MT; }
 // Waves per block of the first product: fp64 takes eight one-subtile waves
 // (two per SIMD, so that one multiplies while the other waits at a stage
-// boundary; its registers allow it), fp32 G1_WAVES two-subtile waves.
+// boundary; its registers allow it), fp32 G1_WAVES waves of G1_MT subtiles.
 template <typename T> constexpr int g1_waves() { return sizeof(T) == 8 ? 8 : G1_WAVES; }
 // Depth of the register prefetch ring of gemm2.
 constexpr int G2_STAGES_F32 = 3;
@@ -93,8 +102,8 @@ struct PackAArgs {
   T* Apad; int64_t ldap;   // rp columns of ldap rows
 };
 
-// k values per gemm1 chunk (one G1_RUN-byte run per column)
-template <typename T> constexpr int g1_chunk() { return G1_RUN / (int)sizeof(T); }
+// k values per gemm1 chunk (one g1_run<T>()-byte run per column)
+template <typename T> constexpr int g1_chunk() { return g1_run<T>() / (int)sizeof(T); }
 
 // The model terms work on ng independent models of r columns each, stored
 // side by side (model m = columns m*r .. m*r + r - 1 of A, lambda, G_A).

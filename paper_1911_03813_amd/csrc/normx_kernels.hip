@@ -24,12 +24,14 @@ __device__ __forceinline__ void tri_pair(int64_t b, int64_t T, int64_t& tr, int6
   tc = t + (b - start(t));
 }
 
-// Elements i .. i+3 of a column of n (zero past n, and all zero when !ok),
-// without branches.  VEC (16-byte aligned columns, leading dimension a
-// multiple of 4 elements, so a column holds 4 ceil(n/4) elements): one vector
-// load of the quad clamped into the column; otherwise four clamped loads.
+// Elements i .. i+3 of a column of n, loaded from addresses clamped into the
+// column, without branches.  VEC (16-byte aligned columns, leading dimension
+// a multiple of 4 elements, so a column holds 4 ceil(n/4) elements): one
+// vector load of the quad; otherwise four loads.  Element e is valid only
+// when i + e < n (and the column exists): nx_elem zeroes the rest where the
+// quad is used, so that the load itself is not waited for when it is issued.
 template <typename S, bool VEC>
-__device__ __forceinline__ void nx_load(Quad<S>& q, const S* col, int64_t i, int64_t n, bool ok) {
+__device__ __forceinline__ void nx_load(Quad<S>& q, const S* col, int64_t i, int64_t n) {
   if constexpr (VEC) {
     const int64_t n4 = (n + 3) & ~(int64_t)3;
     vload4(q, col + (i < n4 ? i : n4 - 4));
@@ -37,8 +39,10 @@ __device__ __forceinline__ void nx_load(Quad<S>& q, const S* col, int64_t i, int
 #pragma unroll
     for (int e = 0; e < 4; ++e) q.e[e] = gload(col + min(i + e, n - 1));
   }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) q.e[e] = (ok && i + e < n) ? q.e[e] : S(0);
+}
+template <typename S>
+__device__ __forceinline__ double nx_elem(const Quad<S>& q, int e, int64_t i, int64_t n, bool ok) {
+  return (ok && i + e < n) ? (double)q.e[e] : 0.0;
 }
 
 // tile pair b of data set a, weighted, into *out (a whole block of 256 threads)
@@ -67,24 +71,69 @@ __device__ __forceinline__ void normx_pair(const NormXArgs<S>& a, int64_t b, dou
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[m][q] = acc_t{0, 0, 0, 0};
+  // the accumulators stay in AGPRs (left to the compiler, all of them are
+  // copied to VGPRs and back at every 16-k step)
+  auto pin = [&]() {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) asm("" : "+a"(acc[m][q]));
+  };
+  pin();
 
+  // the 16-k steps' row and column quads come through a register ring three
+  // deep: the loads of step s + 2 are issued before step s is multiplied.
+  // Steps past n load clamped addresses and are zero-filled (never used).
   const int64_t n = a.n;
-  Quad<S> rq[4], cq[4];
-  for (int64_t i0 = 0; i0 < n; i0 += 16) {
+  auto load = [&](Quad<S> (&rq)[4], Quad<S> (&cq)[4], int64_t i0) {
     const int64_t i = i0 + 4 * g;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      nx_load<S, VEC>(rq[m], rp[m], i, n, rok[m]);
-      nx_load<S, VEC>(cq[m], cp[m], i, n, cok[m]);
+      nx_load<S, VEC>(rq[m], rp[m], i, n);
+      nx_load<S, VEC>(cq[m], cp[m], i, n);
     }
+  };
+  auto step = [&](const Quad<S> (&rq)[4], const Quad<S> (&cq)[4], int64_t i0) {
+    const int64_t i = i0 + 4 * g;
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s) {
+      double x[4], y[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        x[m] = nx_elem(rq[m], s, i, n, rok[m]);
+        y[m] = nx_elem(cq[m], s, i, n, cok[m]);
+      }
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          acc[m][q] = Mfma<double>::mac((double)rq[m].e[s], (double)cq[q].e[s], acc[m][q]);
+        for (int q = 0; q < 4; ++q) acc[m][q] = Mfma<double>::mac(x[m], y[q], acc[m][q]);
+    }
+    pin();
+  };
+  Quad<S> ra[4], ca[4], rb[4], cb[4], rc[4], cc[4];
+  load(ra, ca, 0);
+  load(rb, cb, 16);
+  int64_t i0 = 0;
+  // (the scheduling barriers keep each step's loads where they are written:
+  // left to itself the scheduler sinks them to the end of the loop body and
+  // the next step then waits for nearly every load in flight)
+  for (; i0 + 32 < n; i0 += 48) {          // three steps, each reaching below n
+    load(rc, cc, i0 + 32);
+    __builtin_amdgcn_sched_barrier(0);
+    step(ra, ca, i0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(ra, ca, i0 + 48);
+    __builtin_amdgcn_sched_barrier(0);
+    step(rb, cb, i0 + 16);
+    __builtin_amdgcn_sched_barrier(0);
+    load(rb, cb, i0 + 64);
+    __builtin_amdgcn_sched_barrier(0);
+    step(rc, cc, i0 + 32);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  // now i0 + 32 >= n: at most two steps remain, held in ra/ca and rb/cb
+  if (i0 < n) step(ra, ca, i0);
+  if (i0 + 16 < n) step(rb, cb, i0 + 16);
 
   // acc[m][q][v] = (V'V)[rbase + 16m + row(g, v)][cbase + 16q + c]
   double nc[4];

@@ -32,7 +32,10 @@ def gpu_alpha(ctx, V, nu, d, kind):
 
 
 @pytest.mark.parametrize("n,p,d", [(1, 1, 3), (10, 750, 3), (7, 129, 2), (33, 300, 4), (100, 5000, 4),
-                                   (257, 1000, 5), (1000, 4000, 3), (40, 600, 11), (40, 600, 16)])
+                                   (257, 1000, 5), (1000, 4000, 3), (40, 600, 11), (40, 600, 16),
+                                   # 2 to 6 steps of 16 covariates: every exit of the three-deep load ring
+                                   (17, 300, 3), (48, 200, 3), (49, 200, 3), (64, 130, 4), (80, 250, 4),
+                                   (96, 260, 3)])
 @pytest.mark.parametrize("kind", ["f64", "f32"])
 def test_normx_parity(ctx, n, p, d, kind):
     print(f"case n={n} p={p} d={d} kind={kind}", flush=True)

@@ -76,6 +76,15 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
   for (int q = 0; q < QB; ++q)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[q][t] = acc_t{0, 0, 0, 0};
+  // the accumulators stay in AGPRs (left to the compiler, the fp64 ones are
+  // copied to VGPRs and back at every step)
+  auto pin = [&]() {
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) asm("" : "+a"(acc[q][t]));
+  };
+  pin();
   for (int64_t k0 = 0; k0 < n; k0 += 16) {
     const int64_t k = k0 + 4 * g;
     Quad<T> v[QB];
@@ -93,6 +102,7 @@ __device__ void ggemm1_body(const GInst<T>& I, int tile, int cg, double (*red)[G
       for (int q = 0; q < QB; ++q)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[q][t] = Mfma<T>::mac(v[q].e[s], a[t].e[s], acc[q][t]);
+    pin();
   }
   // epilogue per block: acc[q][t][v] = z at l = 16 b + row(g, v), column
   // col0 + 16 t + c.  w = nu z^(d-1) in the storage precision (the exponent
@@ -164,6 +174,14 @@ __device__ void ggemm2_body(const GInst<T>& I, int rb, int split, int cg) {
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
+  // the accumulators stay in AGPRs, as in ggemm1_body
+  auto pin = [&]() {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) asm("" : "+a"(acc[m][t]));
+  };
+  pin();
   for (int64_t b = b0; b < b1; ++b) {
     Quad<T> w[NT];
 #pragma unroll
@@ -185,6 +203,7 @@ __device__ void ggemm2_body(const GInst<T>& I, int rb, int split, int cg) {
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = Mfma<T>::mac(v[s].e[m], w[t].e[s], acc[m][t]);
+    pin();
   }
   // acc[m][t][v] = Y[ibase + 4 row(g, v) + m][col0 + 16 t + c]
   const int64_t rp = (int64_t)I.nt * 16;

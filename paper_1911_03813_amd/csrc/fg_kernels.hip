@@ -44,9 +44,11 @@ namespace symtd {
 //
 // When the observations are 16-byte aligned with n a multiple of 4, the
 // chunk's 16-byte pieces go from global memory straight into LDS
-// (global_load_lds): every lane fetches the piece whose LDS slot is its own,
-// and every thread issues the same number of pieces per chunk, so a wave can
-// wait for exactly one chunk with vmcnt.  Chunks rotate through g1_stages<T>()
+// (global_load_lds), issued by the first g1_dma_waves<T>() waves (all when
+// 0): every lane of those fetches the piece whose LDS slot is its own, and
+// each of their threads issues the same number of pieces per chunk, so a
+// wave can wait for exactly one chunk with vmcnt (the other waves have
+// nothing in flight; the stage barrier publishes the pieces to them).  Chunks rotate through g1_stages<T>()
 // LDS stages: with two, the next chunk is in flight while one is multiplied
 // (with three, the next two).  Other
 // layouts pass through registers with two stages.  The factors are read from
@@ -95,8 +97,12 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   constexpr int VCOLS = 16 * MT * NW;            // observation columns of a block slab
   constexpr int VQ = VCOLS * QPC;                // quads of a chunk
   constexpr int AQ = 16 * NT * QPC;
-  constexpr int VP = (VQ * H + NTH - 1) / NTH;   // 16-byte pieces per thread and chunk
-  constexpr int AP = (AQ * H + NTH - 1) / NTH;
+  // the first DW waves move the chunks (one per SIMD when DW = NW / 2, so
+  // that the other wave on each SIMD keeps multiplying while they issue)
+  constexpr int DW = (g1_dma_waves<T>() > 0 && g1_dma_waves<T>() < NW) ? g1_dma_waves<T>() : NW;
+  constexpr int DT = 64 * DW;                    // threads that move chunks
+  constexpr int VP = (VQ * H + DT - 1) / DT;     // 16-byte pieces per moving thread and chunk
+  constexpr int AP = (AQ * H + DT - 1) / DT;
   constexpr int DPC = VP + AP;                   // DMA instructions per thread and chunk
   constexpr int PART = NW * MT * NT * 4 * 64;    // elements of one block's published partial
   static_assert(NS == 2 || NS == 3, "the chunk loop below is written for two or three stages");
@@ -110,8 +116,9 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
   // LDS stages as distinct objects, so that the compiler can tell the loads
   // filling one stage from the reads of another; each is padded to whole
   // rounds of pieces so that every thread moves the same number of them
-  __shared__ Quad<T> lv0[VP * NTH / H], lv1[VP * NTH / H], lv2[NS > 2 ? VP * NTH / H : 1];
-  __shared__ Quad<T> la0[AP * NTH / H], la1[AP * NTH / H], la2[NS > 2 ? AP * NTH / H : 1];
+  constexpr int LVQ = DMA ? VP * DT / H : VQ, LAQ = DMA ? AP * DT / H : AQ;
+  __shared__ Quad<T> lv0[LVQ], lv1[LVQ], lv2[NS > 2 ? LVQ : 1];
+  __shared__ Quad<T> la0[LAQ], la1[LAQ], la2[NS > 2 ? LAQ : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -145,10 +152,11 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
 
   // DMA of chunk kc of slab sl into one stage (same instruction count on every thread)
   auto dma = [&](Quad<T>* lv, Quad<T>* la, int64_t sl, int64_t kc) {
+    if (DW < NW && wave >= DW) return;            // wave-uniform
     const int64_t k0 = kc * KCH;
 #pragma unroll
     for (int i = 0; i < VP; ++i) {
-      const int P16 = tid + NTH * i;
+      const int P16 = tid + DT * i;
       const T* src = a.V;                         // padding pieces: any valid address
       if (P16 < VQ * H) {
         int col, q;
@@ -158,11 +166,11 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
         src = vcolumn(sl, col) + k + (P16 % H) * (4 / H);
       }
       __builtin_amdgcn_global_load_lds((const void*)src,
-          (__attribute__((address_space(3))) void*)((char*)lv + 16 * (NTH * i + 64 * wave)), 16, 0, 0);
+          (__attribute__((address_space(3))) void*)((char*)lv + 16 * (DT * i + 64 * wave)), 16, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < AP; ++i) {
-      const int P16 = tid + NTH * i;
+      const int P16 = tid + DT * i;
       const T* src = a.Apad;
       if (P16 < AQ * H) {
         int col, q;
@@ -170,7 +178,7 @@ __global__ __launch_bounds__(64 * g1_waves<T>()) void k_gemm1(G1Args<T> a) {
         src = a.Apad + (int64_t)(a.col0 + col) * a.ldap + k0 + 4 * q + (P16 % H) * (4 / H);
       }
       __builtin_amdgcn_global_load_lds((const void*)src,
-          (__attribute__((address_space(3))) void*)((char*)la + 16 * (NTH * i + 64 * wave)), 16, 0, 0);
+          (__attribute__((address_space(3))) void*)((char*)la + 16 * (DT * i + 64 * wave)), 16, 0, 0);
     }
   };
 

@@ -32,6 +32,15 @@ constexpr int NT_MAX_G2_F64 = 7;
 #ifndef SYMTD_G1_STAGES
 #define SYMTD_G1_STAGES 3
 #endif
+// waves of a gemm1 block that move the chunks into LDS (0: all of them):
+// fp32 the first four (one per SIMD, so that the other wave on each SIMD
+// keeps the matrix core busy while they issue), fp64 all eight
+#ifndef SYMTD_G1_DMA_WAVES
+#define SYMTD_G1_DMA_WAVES 4
+#endif
+#ifndef SYMTD_G1_DMA_WAVES_F64
+#define SYMTD_G1_DMA_WAVES_F64 0
+#endif
 #ifndef SYMTD_G1_RUN_F64
 #define SYMTD_G1_RUN_F64 256
 #endif
@@ -42,6 +51,7 @@ constexpr int G1_WAVES = SYMTD_G1_WAVES;
 constexpr int G1_MT = SYMTD_G1_MT;
 template <typename T> constexpr int g1_run() { return sizeof(T) == 8 ? SYMTD_G1_RUN_F64 : SYMTD_G1_RUN; }
 template <typename T> constexpr int g1_stages() { return sizeof(T) == 8 ? SYMTD_G1_STAGES_F64 : SYMTD_G1_STAGES; }
+template <typename T> constexpr int g1_dma_waves() { return sizeof(T) == 8 ? SYMTD_G1_DMA_WAVES_F64 : SYMTD_G1_DMA_WAVES; }
 // M subtiles per wave of the first product: fp64 takes one, so that seven
 // column subtiles of fp64 accumulators fit the register file and r <= 112
 // needs one launch (V read once)

@@ -177,24 +177,35 @@ __global__ __launch_bounds__(256) void k_gnormx(const GNormX<S>* sets, const Nor
   normx_pair<S, true>(a, it.pair, a.part + it.pair);
 }
 
-// the partials of one set summed: thread-strided, then a fixed tree
+// the partials of one set summed in a fixed order: each thread takes a
+// strided share, eight loads in flight per round (added pairwise), then a
+// tree over the block
+constexpr int REDUCE_THREADS = 1024;
 __device__ __forceinline__ void reduce_body(const double* part, int64_t count, double* out) {
-  __shared__ double s[256];
+  __shared__ double s[REDUCE_THREADS];
+  constexpr int R = REDUCE_THREADS;
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < count; e += 256) acc += part[e];
+  int64_t e = threadIdx.x;
+  for (; e + 7 * R < count; e += 8 * R) {
+    double v[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) v[h] = part[e + h * R];
+    acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  }
+  for (; e < count; e += R) acc += part[e];
   s[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = R / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = s[0];
 }
 
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) { reduce_body(a.part, a.count, a.out); }
+__global__ __launch_bounds__(REDUCE_THREADS) void k_reduce(ReduceArgs a) { reduce_body(a.part, a.count, a.out); }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_greduce(const GNormX<S>* sets) {
+__global__ __launch_bounds__(REDUCE_THREADS) void k_greduce(const GNormX<S>* sets) {
   const GNormX<S> g = sets[blockIdx.x];
   reduce_body(g.a.part, g.pairs, g.alpha);
 }
@@ -208,14 +219,14 @@ void launch_normx(bool vec, dim3 grid, hipStream_t st, const NormXArgs<double>& 
   else hipLaunchKernelGGL((k_normx<double, false>), grid, dim3(256), 0, st, a);
 }
 void launch_reduce(hipStream_t st, const ReduceArgs& a) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(REDUCE_THREADS), 0, st, a);
 }
 template <typename S>
 static void launch_normx_grouped_t(int nitems, int nsets, hipStream_t st, const GNormX<S>* sets,
                                    const NormXItem* items) {
   if (nitems <= 0 || nsets <= 0) return;
   hipLaunchKernelGGL(k_gnormx<S>, dim3(nitems), dim3(256), 0, st, sets, items);
-  hipLaunchKernelGGL(k_greduce<S>, dim3(nsets), dim3(256), 0, st, sets);
+  hipLaunchKernelGGL(k_greduce<S>, dim3(nsets), dim3(REDUCE_THREADS), 0, st, sets);
 }
 void launch_normx_grouped(int nitems, int nsets, hipStream_t st, const GNormX<float>* sets, const NormXItem* items) {
   launch_normx_grouped_t(nitems, nsets, st, sets, items);

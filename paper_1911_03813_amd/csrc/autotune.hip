@@ -189,19 +189,36 @@ symtd_status symtd_autotune_fg(symtd_ctx* ctx, void* stream, symtd_dtype dt, con
   std::sort(c2.begin(), c2.end());
   c2.erase(std::unique(c2.begin(), c2.end()), c2.end());
   const int64_t keep1 = ctx->tune_g1_blocks, keep2 = ctx->tune_g2_splits;
-  double best = INFINITY;
-  int64_t b1 = c1.back(), b2 = base;
+  // every candidate is timed once in each of kRounds rounds, the candidates
+  // in turn, so that a drift of clocks or caches over the sweep reaches them
+  // all alike; a candidate's time is its median over the rounds
+  struct Cand {
+    int64_t x1, x2;
+    std::vector<double> t;
+  };
+  std::vector<Cand> cs;
   for (int64_t x1 : c1)
-    for (int64_t x2 : c2) {
-      if (s != SYMTD_OK) break;
-      ctx->tune_g1_blocks = x1;
-      ctx->tune_g2_splits = x2;
+    for (int64_t x2 : c2) cs.push_back(Cand{x1, x2, {}});
+  constexpr int kRounds = 5;
+  for (int round = 0; round < kRounds && s == SYMTD_OK; ++round)
+    for (Cand& cd : cs) {
+      ctx->tune_g1_blocks = cd.x1;
+      ctx->tune_g2_splits = cd.x2;
       double sec = 0.0;
       s = time_calls(ctx, st, reps, [&]() {
         return symtd_fg(ctx, stream, dt, V, ldv, nu, n, p, A, lda, lambda, r, d, 0.0, prec, f, g, G, n);
       }, &sec);
-      if (s == SYMTD_OK && sec < best) { best = sec; b1 = x1; b2 = x2; }
+      if (s != SYMTD_OK) break;
+      cd.t.push_back(sec);
     }
+  double best = INFINITY;
+  int64_t b1 = c1.back(), b2 = base;
+  for (Cand& cd : cs) {
+    if (cd.t.empty()) continue;
+    std::sort(cd.t.begin(), cd.t.end());
+    const double med = cd.t[cd.t.size() / 2];
+    if (med < best) { best = med; b1 = cd.x1; b2 = cd.x2; }
+  }
   ctx->tune_g1_blocks = keep1;
   ctx->tune_g2_splits = keep2;
   (void)hipStreamSynchronize(st);

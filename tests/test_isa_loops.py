@@ -8,7 +8,8 @@ gfx950 (device code only, to assembly, with the library's own flags) and
 checks, for the benchmark's instantiations, that the innermost loops holding
 the most MFMA instructions of each kernel contain no accumulator copies and
 no scratch accesses.  A compiler or source change that brings the copies back
-fails here, on the CPU.
+fails here, on the CPU.  (The 16-bit first product's chunk loop holds the
+hand-off's wait loop, so it has no innermost MFMA loop and is not covered.)
 """
 
 import collections
@@ -36,6 +37,10 @@ KERNELS = {
     "normx_kernels.hip": [
         "_ZN5symtd7k_normxIfLb1E",
         "_ZN5symtd7k_normxIdLb1E",
+    ],
+    "lp_kernels.hip": [
+        "_ZN5symtd10k_lp_gemm2ILi0ELi7E",      # fp16 second product
+        "_ZN5symtd10k_lp_gemm2ILi1ELi7E",      # bf16x3
     ],
     "grouped_kernels.hip": [
         "_ZN5symtd8k_ggemm1IdLb1E",

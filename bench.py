@@ -71,9 +71,9 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_1911_03813_amd/csrc/fg_kernels.hip", "paper_1911_03813_amd/csrc/kernels.hpp",
                    "paper_1911_03813_amd/csrc/kcommon.hpp", "paper_1911_03813_amd/csrc/lp_kernels.hip",
                    "paper_1911_03813_amd/csrc/lp.hpp")
-TRAFFIC_SHA = "32c0b3747e3f649e"
-TRAFFIC_BYTES = {("fp32", "gemm1"): 507.9e6, ("fp32", "gemm2"): 468.7e6,
-                 ("fp64", "gemm1"): 1093.3e6, ("fp64", "gemm2"): 932.5e6,
+TRAFFIC_SHA = "72b7bcb35ce945af"
+TRAFFIC_BYTES = {("fp32", "gemm1"): 506.8e6, ("fp32", "gemm2"): 468.0e6,
+                 ("fp64", "gemm1"): 1092.8e6, ("fp64", "gemm2"): 932.6e6,
                  ("fp16", "gemm1"): 273.5e6, ("fp16", "gemm2"): 242.3e6,
                  ("bf16x3", "gemm1"): 509.0e6, ("bf16x3", "gemm2"): 469.7e6}
 

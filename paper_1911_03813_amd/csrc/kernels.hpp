@@ -18,8 +18,8 @@ constexpr int NT_MAX_G2_F64 = 7;
 // gemm1 shape of the fp32 kernel: waves per block, M subtiles (16
 // observations) per wave, bytes of one column run per chunk, and LDS stages
 // of the chunk ring; and the chunk run and stages of the fp64 kernel.
-// fp32: eight one-subtile waves (two per SIMD) on 128-byte chunks in three
-// stages (96 KiB of LDS); fp64: 256-byte chunks in two stages (128 KiB).
+// fp32: eight one-subtile waves (two per SIMD) on 256-byte chunks in two
+// stages (120 KiB of LDS); fp64: 256-byte chunks in two stages (128 KiB).
 #ifndef SYMTD_G1_WAVES
 #define SYMTD_G1_WAVES 8
 #endif
@@ -27,10 +27,10 @@ constexpr int NT_MAX_G2_F64 = 7;
 #define SYMTD_G1_MT 1
 #endif
 #ifndef SYMTD_G1_RUN
-#define SYMTD_G1_RUN 128
+#define SYMTD_G1_RUN 256
 #endif
 #ifndef SYMTD_G1_STAGES
-#define SYMTD_G1_STAGES 3
+#define SYMTD_G1_STAGES 2
 #endif
 // waves of a gemm1 block that move the chunks into LDS (0: all of them):
 // fp32 the first four (one per SIMD, so that the other wave on each SIMD
